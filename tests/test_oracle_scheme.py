@@ -1,0 +1,279 @@
+"""Scheme-level pins of the oracle: properties the paper's method fixes exactly
+or in closed form (Sec. 2.1, 3.1-3.4), independent of the oracle's own code."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2005_08736_amd import cases
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+GAMMA = 1.4
+
+
+def smooth_random_field(nx, ny, nz, seed=0, amp=0.05):
+    """Smooth periodic state built from a few low Fourier modes (not a case of
+    the paper; used only for symmetry and conservation checks)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx * 2 * math.pi
+    y = (np.arange(ny) + 0.5) / ny * 2 * math.pi
+    z = (np.arange(nz) + 0.5) / nz * 2 * math.pi
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    def f():
+        a = rng.normal(size=6)
+        return (a[0] * np.sin(X + a[1]) + a[2] * np.cos(Y + 2 * Z + a[3]) + a[4] * np.sin(2 * X - Y + a[5]))
+    rho = 1.0 + amp * f()
+    U, V, W = 0.3 + amp * f(), -0.2 + amp * f(), 0.1 + amp * f()
+    p = 1.0 + amp * f()
+    q = np.empty((5, nz, ny, nx))
+    q[0] = rho
+    q[1], q[2], q[3] = rho * U, rho * V, rho * W
+    q[4] = p / (GAMMA - 1) + 0.5 * rho * (U * U + V * V + W * W)
+    return q
+
+
+def prm_for(q, **kw):
+    nz, ny, nx = q.shape[1:]
+    base = dict(nx=nx, ny=ny, nz=nz, lx=2 * math.pi, ly=2 * math.pi * ny / nx, lz=2 * math.pi * nz / nx,
+                mu_ref=2e-3, prandtl=0.72)
+    base.update(kw)
+    return cases.params(**base)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_uniform_flow_preserved_bitwise(oracle_mod, mode):
+    q = cases.uniform_state(7, 8, 6, rho=1.3, vel=(0.4, -0.7, 0.25), p=0.9)
+    p = prm_for(q, mode=mode)
+    q1, dts = oracle_mod.step(p, q, 3)
+    assert np.array_equal(q1, q)
+    assert dts[0] > 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_conservation_to_roundoff(oracle_mod, mode):
+    q = smooth_random_field(12, 10, 8, seed=1)
+    p = prm_for(q, mode=mode)
+    tot0 = q.reshape(5, -1).sum(axis=1)
+    scale = np.abs(q).reshape(5, -1).sum(axis=1)
+    q1, _ = oracle_mod.step(p, q, 3)
+    tot1 = q1.reshape(5, -1).sum(axis=1)
+    assert np.all(np.abs(tot1 - tot0) / scale <= 3 * 1e-14), (tot1 - tot0) / scale
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_operator_cyclic_axis_symmetry(oracle_mod, mode):
+    # relabel axes (x, y, z) -> (y, z, x): the scheme's result must relabel the same way
+    q = smooth_random_field(8, 8, 8, seed=2)
+    p = prm_for(q, mode=mode)
+    L, dL = oracle_mod.operator(p, q, dt=0.01)
+    # new field: q'(x', y', z') with x' = y, y' = z, z' = x  and velocity (V, W, U)
+    qp = np.empty_like(q)
+    perm = lambda a: np.transpose(a, (2, 0, 1))  # [z][y][x] -> [x][z][y] i.e. new [z'][y'][x']
+    qp[0] = perm(q[0])
+    qp[1], qp[2], qp[3] = perm(q[2]), perm(q[3]), perm(q[1])
+    qp[4] = perm(q[4])
+    Lp, dLp = oracle_mod.operator(p, qp, dt=0.01)
+    for comp_new, comp_old in [(0, 0), (1, 2), (2, 3), (3, 1), (4, 4)]:
+        for A, Ap in ((L, Lp), (dL, dLp)):
+            ref = perm(A[comp_old])
+            assert np.allclose(Ap[comp_new], ref, rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_operator_mirror_symmetry(oracle_mod, mode):
+    # x -> -x with U -> -U: the result mirrors, with the x-momentum changing sign
+    q = smooth_random_field(8, 6, 6, seed=3)
+    p = prm_for(q, mode=mode)
+    L, dL = oracle_mod.operator(p, q, dt=0.01)
+    qm = q[:, :, :, ::-1].copy()
+    qm[1] *= -1
+    Lm, dLm = oracle_mod.operator(p, qm, dt=0.01)
+    for A, Am in ((L, Lm), (dL, dLm)):
+        ref = A[:, :, :, ::-1].copy()
+        ref[1] *= -1
+        assert np.allclose(Am, ref, rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+def test_shear_wave_decays_at_the_viscous_rate(oracle_mod):
+    # U = 0, V = A sin x, uniform rho, p: the Navier-Stokes equations reduce to the
+    # heat equation for V, and the kinetic flux carries the stress mu dV/dx with
+    # mu = tau p.  Two facts of the method fix the discrete decay exactly:
+    #  * dV/dx at a face is the derivative of the cubic through four cell averages,
+    #    whose modified wavenumber on sin gives k_eff^2 below;
+    #  * the time derivative of the smooth flux holds only the inviscid part
+    #    (F1 = Jacobian times the Euler dQ/dt, which vanishes here), so the
+    #    two-stage step advances the viscous term as a forward-Euler step.
+    n, A, nu, T = 32, 1e-3, 0.02, 0.5
+    p = cases.params(nx=n, ny=6, nz=6, lx=2 * math.pi, ly=2 * math.pi * 6 / n, lz=2 * math.pi * 6 / n,
+                     mu_ref=nu, prandtl=0.72, cfl=0.4)
+    x = (np.arange(n) + 0.5) * 2 * math.pi / n
+    h = 2 * math.pi / n
+    q = cases.uniform_state(n, 6, 6, rho=1.0, vel=(0, 0, 0), p=1.0 / GAMMA)
+    vbar = A * np.sin(x) * math.sin(h / 2) / (h / 2)  # exact cell averages
+    q[2] = vbar[None, None, :]
+    q[4] += 0.5 * q[2] ** 2
+    steps = 20
+    dt = T / steps
+    q1, _ = oracle_mod.step(p, q, steps, dt=dt)
+    ratio = np.sum(q1[2, 0, 0] * vbar) / np.sum(vbar * vbar)
+    k2 = (30 * math.sin(h / 2) - 2 * math.sin(1.5 * h)) * 2 * math.sin(h / 2) / (12 * h * h)
+    expected = (1 - nu * k2 * dt) ** steps
+    assert abs(ratio - expected) < 1e-9, (ratio, expected)
+    assert abs(ratio - math.exp(-nu * T)) < 5e-6  # and close to the continuous decay
+
+
+def _wave_error(oracle_mod, n, diagonal, t_end, mode=0):
+    prm = cases.density_wave_params(n, diagonal=diagonal, mode=mode)
+    q = cases.density_wave_state(prm, 0.0, diagonal=diagonal)
+    h = 2.0 / n
+    dt0 = 0.4 * h / (2.2 if not diagonal else 2.2)
+    dt = 0.4 * (2.0 / 16) / 2.2 * (h / (2.0 / 16)) ** 1.25  # dt ~ h^(5/4)
+    dt = min(dt, dt0)
+    steps = int(math.ceil(t_end / dt))
+    dt = t_end / steps
+    q1, _ = oracle_mod.step(prm, q, steps, dt=dt)
+    exact = cases.density_wave_state(prm, t_end, diagonal=diagonal)
+    return np.sqrt(np.mean((q1[0] - exact[0]) ** 2))
+
+
+def test_design_order_density_wave_along_x(oracle_mod):
+    errs = [_wave_error(oracle_mod, n, False, 0.5) for n in (16, 32, 64)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] >= 4.6, (errs, orders)
+
+
+@pytest.mark.slow
+def test_design_order_density_wave_diagonal(oracle_mod):
+    errs = [_wave_error(oracle_mod, n, True, 0.25) for n in (8, 16, 32)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] >= 3.7, (errs, orders)
+
+
+def test_density_wave_order_mode_z(oracle_mod):
+    errs = [_wave_error(oracle_mod, n, False, 0.25, mode=1) for n in (16, 32, 64)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] >= 4.0, (errs, orders)
+
+
+def test_tgv_time_step_matches_paper_table(oracle_mod):
+    g = GOLD["tgv_time_step"]
+    for n, dt_printed in zip(g["n"], g["dt"]):
+        if n > 128:
+            continue  # the 256^3 / 512^3 fields are too large for the CPU suite
+        p = cases.tgv_params(n)
+        dt = oracle_mod.cfl_dt(p, cases.tgv_state(n))
+        assert abs(dt - dt_printed) <= 0.5e-3 * dt_printed, (n, dt, dt_printed)
+
+
+def test_tgv_early_decay_converges_to_the_viscous_rate(oracle_mod):
+    # E_k(t) ~ E_k(0) exp(-6 nu t) at early times (each initial mode has |k|^2 = 3);
+    # numerical dissipation makes the 16^3 run decay faster, and the excess must
+    # shrink at high order with refinement.
+    nu = 1.0 / 1600.0
+    rel = {}
+    for n, steps in ((16, 10), (32, 20)):
+        p = cases.tgv_params(n)
+        q = cases.tgv_state(n)
+        d0 = oracle_mod.diagnostics(p, q)
+        q1, dts = oracle_mod.step(p, q, steps)
+        d1 = oracle_mod.diagnostics(p, q1)
+        T = dts.sum()
+        dS = d0["E_k"] * (math.exp(-6 * nu * T) - 1)
+        rel[n] = (d1["E_k"] - d0["E_k"] - dS) / dS
+        assert abs(T - 0.1433) < 2e-3
+    assert 0 < rel[32] < 0.1, rel
+    assert rel[16] / rel[32] > 8, rel
+
+
+def test_diagnostics_closed_forms_single_modes(oracle_mod):
+    n = 16
+    h = 2 * math.pi / n
+    x = (np.arange(n) + 0.5) * h
+    kap = (45 * math.sin(h) - 9 * math.sin(2 * h) + math.sin(3 * h)) / (30 * h)  # 6th-order modified wavenumber
+    mu = 0.01
+    Kd = (5 - 3 * GAMMA) / (GAMMA - 1)
+    p = cases.params(nx=n, ny=n, nz=n, mu_ref=mu, prandtl=0.72)
+    # shear mode: U = A sin y, rho = 1, p uniform
+    A, p0 = 0.3, 2.0
+    q = np.zeros((5, n, n, n))
+    q[0] = 1.0
+    q[1] = A * np.sin(x)[None, :, None]
+    q[4] = p0 / (GAMMA - 1) + 0.5 * q[1] ** 2
+    d = oracle_mod.diagnostics(p, q)
+    assert abs(d["E_k"] - A * A / 4) < 1e-14
+    assert abs(d["zeta"] - A * A * kap * kap / 4) < 1e-13
+    assert abs(d["eps1"] - mu * A * A * kap * kap / 2) < 1e-14
+    assert abs(d["eps2"]) < 1e-15 and abs(d["eps3"]) < 1e-13
+    assert abs(d["u_rms"] - math.sqrt(A * A / 6)) < 1e-14
+    # dilatational mode: U = A sin x, p = p0 + d cos x
+    dp = 0.1
+    q = np.zeros((5, n, n, n))
+    q[0] = 1.0
+    q[1] = A * np.sin(x)[None, None, :]
+    pf = p0 + dp * np.cos(x)[None, None, :]
+    q[4] = pf / (GAMMA - 1) + 0.5 * q[1] ** 2
+    d = oracle_mod.diagnostics(p, q)
+    mub = 2 * Kd / (3 * (Kd + 3)) * mu
+    assert abs(mub - 4.0 / 15.0 * mu) < 1e-17  # Sec. 3.1 with N = 2
+    assert abs(d["eps1"] - 2 * mu * (2.0 / 3.0) * A * A * kap * kap / 2) < 1e-14
+    assert abs(d["eps2"] - mub * A * A * kap * kap / 2) < 1e-14
+    assert abs(d["eps3"] - (-dp * A * kap / 2)) < 1e-13
+    assert abs(d["S_u"]) < 1e-12
+    assert abs(d["F_u"] - 1.5) < 1e-12  # <cos^4>/<cos^2>^2 = (3/8)/(1/4)
+
+
+def test_jvp_matches_central_differences(oracle_mod):
+    q = smooth_random_field(6, 6, 6, seed=4)
+    p = prm_for(q, mode=0)
+    rng = np.random.default_rng(5)
+    dq = rng.normal(size=q.shape) * 1e-2
+    dts = np.array([0.02, 0.02])
+    q1, jv = oracle_mod.jvp(p, q, dq, dts)
+    qs, _ = oracle_mod.step(p, q, 2, dt=0.02)
+    assert np.array_equal(q1, qs)
+    eps = 1e-5
+    qp, _ = oracle_mod.step(p, q + eps * dq, 2, dt=0.02)
+    qm, _ = oracle_mod.step(p, q - eps * dq, 2, dt=0.02)
+    fd = (qp - qm) / (2 * eps)
+    assert np.abs(jv - fd).max() <= 1e-7 * np.abs(fd).max()
+
+
+def test_non_physical_state_rejected(oracle_mod):
+    q = cases.uniform_state(6, 6, 6)
+    q[4, 2, 3, 1] = 0.0  # negative pressure in one cell
+    p = prm_for(q)
+    assert oracle_mod.step_rc(p, q, 1) == -3
+    bad = cases.params(nx=5, ny=6, nz=6)
+    assert oracle_mod.step_rc(bad, cases.uniform_state(5, 6, 6), 1) == -1
+
+
+# ---------------------------------------------------------------------------
+# input recipe pins (the paper's printed parameter tables)
+def test_isotropic_parameter_chain_matches_table():
+    g = GOLD["isotropic_re72"]
+    c = cases.isotropic_constants(72.0)
+    n = g["n"]
+    kmax = math.sqrt(2) * n / 3
+    assert abs(kmax * c["eta0"] - g["kappa_max_eta0"]) < 1e-3
+    assert abs((2 * math.pi / n) / c["eta0"] - g["delta_over_eta0"]) < 1e-3
+    for ma, ref in zip(g["ma_t"], g["delta_over_lambda0"]):
+        c0 = math.sqrt(3) * c["u_rms"] / ma
+        lam0 = 3 * c["mu0"] / c0
+        assert abs((2 * math.pi / n) / lam0 - ref) < 1.5e-3, (ma, (2 * math.pi / n) / lam0, ref)
+    # closed forms of Eq. (initial_def)
+    assert abs(c["K0"] - 0.50052) < 1e-5 and abs(c["Omega0"] - 40.042) < 1e-3
+    assert abs(c["tau_to"] - 0.54242) < 1e-5
+
+
+def test_channel_mesh_matches_table():
+    g = GOLD["channel_grids"]
+    for i, n in enumerate(g["n"]):
+        yf, yc = cases.channel_y(n, 2.0)
+        dy = np.diff(yf)
+        scale = g["re_tau"]  # y+ = y u_tau / nu with nu = u_tau / Re_tau and H = 1
+        assert abs(0.5 * dy[0] * scale - g["dy_plus_min"][i]) < 0.006
+        assert abs(dy.max() * scale - g["dy_plus_max"][i]) < 0.015
+        assert abs(2 * math.pi / n * scale - g["dx_plus"][i]) < 0.015
+        assert abs(math.pi / n * scale - g["dz_plus"][i]) < 0.006
