@@ -1,0 +1,174 @@
+"""Throughput benchmark of the HGKS stage update on one MI355X.
+
+Workload: 3-D Taylor-Green vortex, 256^3 cells, FP64, smooth mode (linear-weight
+WENO5 + smooth gas-kinetic flux), gamma = 1.4, Pr = 0.72, Re = 1600, Ma = 0.1,
+CFL 0.4.  One step = one full two-stage update of every cell.  The state is
+resident in HBM before the timed region; the timed region is K calls' worth of
+steps in one hgks_step call bracketed by device synchronisations.
+
+Prints one JSON line.  Extra information goes to stderr.
+
+  python bench.py [--steps K] [--warmup W] [--n 256] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s (FP64 vs FP32-form) at stated L2 error; adjoint step time ratio"
+UNIT = "Mcell-updates/s"
+# The paper's own figure for this workload (TGV 256^3, 64 Xeon E5-2692 cores,
+# Sec. 3.2 Table time_table1: 9.09 s per step): context, on other hardware.
+PAPER_MCUPS_256 = 256 ** 3 / 9.09 / 1e6
+
+# MI355X published peaks (dense, per GPU)
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP64 flops of one face in the stage-1 flux kernel (tangential
+# reconstruction to four Gauss points + four gas-kinetic flux evaluations + face
+# average), counted as executed FP64 VALU operations per face (FMA = 2) by
+# rocprofv3 counters on this kernel source; see profiles/.
+FLUX_STAGE1_FLOPS_PER_FACE = None
+# HBM bytes per face of the stage-1 flux kernel from rocprofv3 FETCH_SIZE +
+# WRITE_SIZE, scaled by the copy-kernel calibration factor; valid only for the
+# kernel source with this digest.
+FLUX_STAGE1_HBM_BYTES_PER_FACE = None
+FLUX_COUNTERS_SOURCE_DIGEST = None
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2005_08736_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_cpu: int, steps: int):
+    """The oracle as it stands, on the host cores, on a bounded sample of the same
+    workload: the Taylor-Green vortex at n_cpu^3 (identical per-cell work)."""
+    import oracle
+    from paper_2005_08736_amd import cases
+
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    p = cases.tgv_params(n_cpu)
+    q = cases.tgv_state(n_cpu)
+    t0 = time.perf_counter()
+    oracle.step(p, q, steps)
+    el = time.perf_counter() - t0
+    return {
+        "value": n_cpu ** 3 * steps / el / 1e6,
+        "unit": UNIT,
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"Taylor-Green {n_cpu}^3, {steps} CFL step(s), FP64, same scheme and per-cell work; {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--cpu-n", type=int, default=96)
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2005_08736_amd import cases, hgks
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a ROCm device")
+    dev = torch.device("cuda:0")
+    n = args.n
+    p = cases.tgv_params(n)
+    log(f"[bench] building Taylor-Green {n}^3 initial state")
+    q = torch.from_numpy(cases.tgv_state(n)).to(dev)
+    s = hgks.Solver(p, q)
+    log(f"[bench] warmup {args.warmup} steps")
+    if args.warmup:
+        s.step(args.warmup)
+    s.profile(True)
+    s.profile_read()  # reset
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    dts = s.step(args.steps, return_dt=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    N = n ** 3
+    value = N * args.steps / el / 1e6
+    ms_per_step = el / args.steps * 1e3
+    log(f"[bench] {ms_per_step:.3f} ms/step, {value:.1f} Mcell-updates/s, dt={dts[0]:.4e}")
+    for k, (ms, cnt) in prof.items():
+        log(f"[bench]   {k:12s} {ms:9.3f} ms total over {cnt} launches ({ms / max(cnt, 1):.4f} ms avg)")
+    ms_flux, cnt_flux = prof["flux_stage1"]
+    avg_flux_s = ms_flux / max(cnt_flux, 1) / 1e3
+    if FLUX_STAGE1_FLOPS_PER_FACE is not None:
+        achieved = FLUX_STAGE1_FLOPS_PER_FACE * N / avg_flux_s / 1e12
+    else:
+        achieved = None
+    traffic = None
+    if FLUX_STAGE1_HBM_BYTES_PER_FACE is not None and FLUX_COUNTERS_SOURCE_DIGEST == kernel_source_digest():
+        traffic = FLUX_STAGE1_HBM_BYTES_PER_FACE * N
+    roofline = {
+        "bound": "alu",
+        "kernel": "face_flux (stage 1)",
+        "achieved": achieved,
+        "peak": PEAK_FP64_VECTOR_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": (achieved / PEAK_FP64_VECTOR_TFLOPS) if achieved is not None else None,
+        "traffic": traffic,
+        "avg_launch_ms": avg_flux_s * 1e3,
+    }
+    d = s.diagnostics()
+    log(f"[bench] after {args.warmup + args.steps} steps: E_k={d['E_k']:.8f} min_p={d['min_p']:.6f}")
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] cpu baseline: oracle on Taylor-Green {args.cpu_n}^3, {args.cpu_steps} step(s)")
+        cpu = cpu_baseline(args.cpu_n, args.cpu_steps)
+        log(f"[bench] cpu baseline {cpu['value']:.4f} Mcell-updates/s on {cpu['cores']} threads")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_MCUPS_256 if n == 256 else None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"taylor_green_{n}^3_fp64_smooth", "cells": N, "cfl": 0.4, "dt": dts[0],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

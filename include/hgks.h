@@ -1,0 +1,154 @@
+/*
+ * hgks.h - C ABI of the MI355X library for the per-stage finite-volume update of
+ * the high-order gas-kinetic scheme (HGKS) of Cao, Pan & Xu, "High-order
+ * gas-kinetic scheme with parallel computation for direct numerical simulation of
+ * turbulent flows", arXiv:2005.08736.
+ *
+ * The library advances the conservative cell averages
+ *     Q = (rho, rho U, rho V, rho W, rho E)
+ * on a structured 3-D box with the two-stage fourth-order scheme of Sec. 2.1,
+ * Eq. (two-stage), whose operator L(Q) = -(1/|Omega|) sum_p F_p (Eq. (finite))
+ * uses 2x2 Gauss points per face and the gas-kinetic flux of Eq. (flux) (the
+ * smooth simplified form of the first Remark of Sec. 2.1 in HGKS_MODE_SMOOTH).
+ *
+ * Conventions
+ *  - State layout: double q[5][nz][ny][nx] (x fastest), device memory, owned by
+ *    the caller, updated in place.
+ *  - Every device buffer (state, workspace, outputs) is allocated by the caller;
+ *    the library never allocates or frees device memory.  The handle itself is
+ *    host memory owned by the library until hgks_destroy.
+ *  - All work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*; NULL = the default stream).  One handle per stream; calls on one
+ *    handle must not overlap.
+ *  - Nondimensional gas: R = 1, T = p / rho, internal degrees of freedom
+ *    K = (5 - 3 gamma)/(gamma - 1), viscosity mu(T) = mu_ref (T/T_ref)^mu_exp,
+ *    collision time tau = mu/p (start of Sec. 3).
+ *  - Every function returns an int status (HGKS_OK or a negative code); no C++
+ *    exception crosses the boundary.
+ */
+#ifndef HGKS_H
+#define HGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HGKS_OK = 0,
+  HGKS_E_INVALID_ARG = -1, /* bad parameter, pointer, size or grid */
+  HGKS_E_DEVICE = -2,      /* a HIP runtime call failed */
+  HGKS_E_NONPHYSICAL = -3, /* rho <= 0, p <= 0 or a non-finite value appeared */
+  HGKS_E_UNSUPPORTED = -4, /* valid but not implemented combination */
+  HGKS_E_WORKSPACE = -5    /* workspace missing, too small or misaligned */
+};
+
+/* HGKS_MODE_SMOOTH: linear-weight WENO5 normal reconstruction, fourth-order
+ *   tangential polynomials and the smooth second-order gas-kinetic flux
+ *   (Remark 1 of Sec. 2.1; the Taylor-Green and channel cases).
+ * HGKS_MODE_WENOZ: WENO-Z reconstruction and the full flux of Eq. (flux) with the
+ *   artificial collision time of Sec. 3 (isotropic turbulence). */
+enum { HGKS_MODE_SMOOTH = 0, HGKS_MODE_WENOZ = 1 };
+/* HGKS_PREC_F64: all arithmetic in FP64.
+ * HGKS_PREC_F32FLUX: reconstruction and flux arithmetic in FP32 around FP64
+ *   anchors, FP64 state and compensated accumulation of the flux divergence. */
+enum { HGKS_PREC_F64 = 0, HGKS_PREC_F32FLUX = 1 };
+enum { HGKS_BC_PERIODIC = 0, HGKS_BC_WALL_ISOTHERMAL = 1 /* y only */ };
+
+/* Number of doubles written by hgks_diagnostics. */
+#define HGKS_NDIAG 34
+
+typedef struct {
+  int32_t nx, ny, nz;      /* cells per axis; >= 6 on every periodic axis */
+  double lx, ly, lz;       /* box lengths (channel: ly = 2, y in [-1, 1]) */
+  int32_t bc_y;            /* HGKS_BC_* for the y axis; x and z are periodic */
+  double stretch_b;        /* 0: uniform y; > 0: tanh map of Sec. 3.3 with b_g */
+  double gamma, prandtl;   /* specific-heat ratio (> 1) and Prandtl number (> 0) */
+  double mu_ref, T_ref, mu_exp; /* mu(T) = mu_ref (T/T_ref)^mu_exp (Sec. 3.4) */
+  int32_t mode;            /* HGKS_MODE_* */
+  double cfl;              /* dt = cfl * min_cells min_d dx_d / (|U_d| + c) */
+  double c_art, weno_eps;  /* artificial collision-time constant C (Sec. 3), WENO-Z epsilon */
+  int32_t weno_p;          /* WENO-Z exponent */
+  double T_wall, body_force_x; /* channel wall temperature; constant body force f_x (Sec. 3.3) */
+  int32_t precision;       /* HGKS_PREC_* */
+} hgks_params;
+
+typedef struct hgks_handle hgks_handle;
+
+/* Bytes of device workspace hgks_init needs for these parameters (0 if the
+ * parameters are invalid).  The workspace must be 256-byte aligned. */
+size_t hgks_workspace_bytes(const hgks_params* p);
+
+/* Validate the parameters, bind the caller's state q (device) and workspace
+ * (device, ws_bytes >= hgks_workspace_bytes(p)) and stream.  No device memory is
+ * allocated.  Errors: HGKS_E_INVALID_ARG (bad parameters, NULL pointers),
+ * HGKS_E_WORKSPACE, HGKS_E_UNSUPPORTED, HGKS_E_DEVICE. */
+int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes, void* hip_stream,
+              hgks_handle** out);
+
+/* Advance the bound state by nsteps two-stage steps (Eq. (two-stage)).  dt > 0:
+ * fixed time step; dt <= 0: each step takes dt from the CFL rule above, computed
+ * on the device from the current state.  dt_taken (host, nsteps doubles) receives
+ * the time steps when not NULL.  The call synchronizes the stream once at the
+ * end.  On HGKS_E_NONPHYSICAL the state holds the last good step and
+ * hgks_failed_step reports the index (0-based, counted over the handle's
+ * lifetime) of the step that produced the bad state. */
+int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken);
+
+/* Operator of Eq. (finite) and its time derivative at an arbitrary state:
+ * L = L(q_in), dL = dL/dt(q_in), all device [5][nz][ny][nx].  dt enters only
+ * mode-Z terms (artificial collision time, time integrals).  Enqueued on the
+ * handle's stream, no synchronization. */
+int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, double* dL);
+
+/* Face fluxes of direction dir (0 = x, 1 = y, 2 = z) of the state q_in: F^n and
+ * dF^n/dt averaged over the face (divide-by-area form: 1/4 sum over the Gauss
+ * points), global frame, face n+1/2 stored at the index of cell n.  Device
+ * [5][nz][ny][nx] each.  A parity aid; no synchronization. */
+int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF);
+
+/* Global FP64 diagnostics of the bound state (Sec. 3.1, 3.4): out (host) receives
+ * HGKS_NDIAG doubles in this order:
+ *   0..4 totals sum Q_k |Omega_i|; 5 E_k; 6 enstrophy zeta; 7 eps1; 8 eps2;
+ *   9 eps3; 10 rho_rms; 11 u_rms; 12 Ma_t; 13 min rho; 14 min p; 15 K;
+ *   16 eps_s; 17 eps_d; 18 <p theta>; 19 mean rho; 20..22 <(d_i U_i)^2>;
+ *   23..25 <(d_i U_i)^3>; 26..28 <(d_i U_i)^4>; 29 S_u; 30 F_u; 31 mean c;
+ *   32 volume; 33 max over cells and axes of (|U_d| + c)/dx_d.
+ * Derivatives use the sixth-order central difference of Sec. 3.1.  Reductions
+ * run in a fixed order, so repeated calls give bitwise-identical results.
+ * Synchronizes the stream. */
+int hgks_diagnostics(hgks_handle* h, double* out);
+
+/* Per-kernel timing.  While enabled, hgks_step brackets every kernel launch with
+ * HIP events recorded on the handle's stream and accumulates the elapsed times
+ * per kernel class (see HGKS_KCLASS_*).  Enabling creates HIP events (host
+ * runtime objects, no workspace use); disabling releases them.  hgks_profile_read
+ * copies the accumulated milliseconds and launch counts of the first n classes
+ * (ms and counts are host arrays of n entries) and resets the accumulators. */
+enum {
+  HGKS_KCLASS_FACE_FIELD = 0, /* normal reconstruction + compatibility state */
+  HGKS_KCLASS_FLUX_STAGE1 = 1, /* tangential reconstruction + Gauss-point flux, stage 1 */
+  HGKS_KCLASS_FLUX_STAGE2 = 2, /* the same, stage 2 (time derivative only) */
+  HGKS_KCLASS_STAGE1 = 3,      /* divergence + Q*, R */
+  HGKS_KCLASS_STAGE2 = 4,      /* divergence + Q^{n+1} + CFL reduction */
+  HGKS_KCLASS_COUNT = 5
+};
+int hgks_profile_enable(hgks_handle* h, int enable);
+int hgks_profile_read(hgks_handle* h, double* ms, int64_t* counts, int n);
+
+/* Index of the step that produced a non-physical state (-1 if none). */
+int hgks_failed_step(const hgks_handle* h);
+
+/* Release the handle (host memory only). */
+void hgks_destroy(hgks_handle* h);
+
+/* Static string for a status code. */
+const char* hgks_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGKS_H */

@@ -1,0 +1,202 @@
+// Device-side building blocks of the HGKS stage update for gfx950 (CDNA4).
+//
+// Scheme: Cao, Pan & Xu, arXiv:2005.08736, Sec. 2.1.  The state is FP64
+// structure-of-arrays q[5][nz][ny][nx]; every kernel maps one thread to one
+// face or cell with x fastest, so each wavefront's loads and stores of a field
+// are 64 consecutive doubles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hgks {
+
+// Grid and gas constants, passed to every kernel by value.
+struct Geo {
+  int n[3];              // cells along x, y, z
+  long long N;           // total cells
+  long long stride[3];   // 1, nx, nx*ny
+  double h[3];           // cell widths
+  double inv_h[3];
+  double gamma, gm1, inv_gm1;
+  double cp;             // gamma / (gamma - 1) with R = 1
+  double inv_pr;         // 1 / Pr
+  double pr_fix;         // 1 / Pr - 1 (heat-flux correction of the BGK model)
+  double mub_m23;        // mu_b/mu - 2/3 with mu_b/mu = 2K/(3(K+3))
+  double K;              // internal degrees of freedom
+  double mu_ref, T_ref, mu_exp;
+  double cfl;
+};
+
+// Control block at the head of the workspace.
+constexpr int kDtHist = 1024;
+struct Ctrl {
+  double dt;                       // time step of the current step
+  double maxspeed;                 // max over cells and axes of (|U_d|+c)/h_d of the step's start state
+  int flag;                        // set to 1 when a non-physical state appears
+  int fail_step;                   // step index that produced it
+  int zero;                        // always 0: "never stop" for the parity entry points
+  int pad;
+  double dt_hist[kDtHist];         // time step of each step of the current call
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction coefficients.
+//
+// Normal direction (face between cells 0 and 1, stencils of cell averages):
+//   left  value: ( 2, -13, 47, 27, -3)/60 on cells -2..2  (fifth-order upwind
+//                 = WENO5 with its optimal linear weights)
+//   right value: mirror image on cells -1..3
+//   derivative : ( 1, -15, 15, -1)/12 on cells -1..2 (derivative at the face of
+//                 the cubic through four averages; adding the face value Q0 as a
+//                 fifth condition leaves it unchanged)
+// Tangential direction: the quartic matching five face averages j-2..j+2,
+// evaluated at the Gauss points s = +-1/(2 sqrt 3) of the middle face.  Written
+// as even/odd parts about the middle so that both Gauss points come from one
+// set of sums:  value(+-) = E +- O,  derivative(+-) = A +- S.
+// ---------------------------------------------------------------------------
+constexpr double kS3 = 1.7320508075688772935;  // sqrt(3)
+// value at s = +1/(2 sqrt 3): even part (centre, +-1, +-2) and odd part (+1, +2)
+constexpr double kVe0 = 719.0 / 720.0;
+constexpr double kVe1 = 1.0 / 1080.0;
+constexpr double kVe2 = -1.0 / 4320.0;
+constexpr double kVo1 = 25.0 * kS3 / 216.0;
+constexpr double kVo2 = -7.0 * kS3 / 432.0;
+// derivative (per unit width) at s = +1/(2 sqrt 3): symmetric part S and antisymmetric part A
+constexpr double kDs0 = -4.0 * kS3 / 9.0;
+constexpr double kDs1 = 13.0 * kS3 / 54.0;
+constexpr double kDs2 = -kS3 / 54.0;
+constexpr double kDa1 = 2.0 / 3.0;
+constexpr double kDa2 = -1.0 / 12.0;
+
+// Tangential reconstruction of one field along a line of five face values f[0..4]
+// (f[2] the middle face): values and derivatives at the -/+ Gauss points.
+template <typename T>
+__device__ __forceinline__ void tang_val(const T* f, T& vm, T& vp) {
+  T e = T(kVe0) * f[2] + T(kVe1) * (f[1] + f[3]) + T(kVe2) * (f[0] + f[4]);
+  T o = T(kVo1) * (f[3] - f[1]) + T(kVo2) * (f[4] - f[0]);
+  vm = e - o;
+  vp = e + o;
+}
+template <typename T>
+__device__ __forceinline__ void tang_der(const T* f, T& dm, T& dp) {
+  T s = T(kDs0) * f[2] + T(kDs1) * (f[1] + f[3]) + T(kDs2) * (f[0] + f[4]);
+  T a = T(kDa1) * (f[3] - f[1]) + T(kDa2) * (f[4] - f[0]);
+  dm = a - s;
+  dp = a + s;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium state at the interface from the two reconstructed states: the
+// compatibility condition of Sec. 2.1 integrates the left Maxwellian over u>0
+// and the right one over u<0.  With lambda = rho/(2p) and the half-space
+// moments of the normal velocity
+//   a0 = erfc(-sqrt(lambda) U)/2, a1 = U a0 + exp(-lambda U^2)/(2 sqrt(pi lambda)),
+//   a2 = U a1 + a0/(2 lambda)
+// (and the mirrored ones for u<0), the psi-moments are
+//   (a0, a1, V a0, W a0, (a2 + a0 (V^2 + W^2 + (K+2)/(2 lambda)))/2).
+// Local frame: component 1 is the face-normal momentum.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void half_maxwell_psi(const T* Q, T gm1, T Kp2, int sgn, T* out) {
+  const T kInvSqrtPi = T(0.56418958354775628695);
+  T rho = Q[0];
+  T ir = T(1) / rho;
+  T U = Q[1] * ir, V = Q[2] * ir, W = Q[3] * ir;
+  T p = gm1 * (Q[4] - T(0.5) * rho * (U * U + V * V + W * W));
+  T lam = T(0.5) * rho / p;
+  T sl = sqrt(lam);
+  T ex = exp(-lam * U * U);
+  T a0, a1;
+  if (sgn > 0) {
+    a0 = T(0.5) * erfc(-sl * U);
+    a1 = U * a0 + T(0.5) * ex * kInvSqrtPi / sl;
+  } else {
+    a0 = T(0.5) * erfc(sl * U);
+    a1 = U * a0 - T(0.5) * ex * kInvSqrtPi / sl;
+  }
+  T i2l = T(0.5) / lam;
+  T a2 = U * a1 + a0 * i2l;
+  out[0] = rho * a0;
+  out[1] = rho * a1;
+  out[2] = rho * V * a0;
+  out[3] = rho * W * a0;
+  out[4] = T(0.5) * rho * (a2 + a0 * (V * V + W * W + Kp2 * i2l));
+}
+
+// ---------------------------------------------------------------------------
+// Smooth gas-kinetic flux at one Gauss point.
+//
+// With a continuous equilibrium g0 on both sides, Eq. (flux) becomes
+//   f = g0 [1 - tau (a_n u + a_t1 v + a_t2 w + A) + t A]
+// and the psi-moments of u f are evaluated here in closed form, taking every
+// moment about the interface velocity (odd central Gaussian moments vanish):
+//   * <u psi> g0           -> the Euler flux of Q0;
+//   * -tau <u (a.u + A) psi> g0 with the slopes a from <a psi> = dQ0/rho0 and A
+//     from <a.u + A> = 0   -> the Newtonian stress with mu = tau p and bulk
+//     viscosity 2K/(3(K+3)) mu, and the Fourier heat flux c_p mu dT (R = 1);
+//   * <u A psi> g0         -> d/dt of the Euler flux along the Euler time
+//     derivative of Q0, i.e. the flux Jacobian times dQ0/dt.
+// The Prandtl-number correction adds (1/Pr - 1) times the heat flux, taken
+// about the interface velocity, of each part of f: -c_p mu dT/dn for the
+// tau-part and c_p p dU_n/dt for the t-part.
+// Inputs (local frame, index 0 = normal): Q0 and its derivatives D[a][k] =
+// dQ0_k/dx_a along (n, t1, t2).  F gets F^n, dF gets dF^n/dt (Eq. (expansion-1)).
+// VAR_MU selects mu(T) = mu_ref (T/T_ref)^mu_exp; otherwise mu = mu_ref (a
+// separate instantiation keeps the power function's registers out of the
+// constant-viscosity kernels).
+// ---------------------------------------------------------------------------
+template <bool NEED_F, bool VAR_MU, typename T>
+__device__ __forceinline__ void smooth_flux(const Geo& g, const T* Q, const T (*D)[5], T* F, T* dF) {
+  const T gm1 = T(g.gm1);
+  T rho = Q[0];
+  T ir = T(1) / rho;
+  T U0 = Q[1] * ir, U1 = Q[2] * ir, U2 = Q[3] * ir;
+  T ke = T(0.5) * (U0 * U0 + U1 * U1 + U2 * U2);
+  T E = Q[4];
+  T p = gm1 * (E - rho * ke);
+  // velocity gradient gu[a][c] = dU_c/dx_a and pressure gradient
+  T gu[3][3], gp[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gu[a][0] = (D[a][1] - U0 * D[a][0]) * ir;
+    gu[a][1] = (D[a][2] - U1 * D[a][0]) * ir;
+    gu[a][2] = (D[a][3] - U2 * D[a][0]) * ir;
+    gp[a] = gm1 * (D[a][4] - (U0 * D[a][1] + U1 * D[a][2] + U2 * D[a][3]) + ke * D[a][0]);
+  }
+  T theta = gu[0][0] + gu[1][1] + gu[2][2];
+  // Euler time derivatives of rho, U, p
+  T rho_t = -(U0 * D[0][0] + U1 * D[1][0] + U2 * D[2][0] + rho * theta);
+  T u_t[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u_t[c] = -(U0 * gu[0][c] + U1 * gu[1][c] + U2 * gu[2][c] + gp[c] * ir);
+  T p_t = -(U0 * gp[0] + U1 * gp[1] + U2 * gp[2] + T(g.gamma) * p * theta);
+  T E_t = p_t * T(g.inv_gm1) + ke * rho_t + rho * (U0 * u_t[0] + U1 * u_t[1] + U2 * u_t[2]);
+  T m0 = rho * U0;
+  dF[0] = rho_t * U0 + rho * u_t[0];
+  dF[1] = rho_t * U0 * U0 + T(2) * m0 * u_t[0] + p_t;
+  dF[2] = rho_t * U0 * U1 + rho * (u_t[0] * U1 + U0 * u_t[1]);
+  dF[3] = rho_t * U0 * U2 + rho * (u_t[0] * U2 + U0 * u_t[2]);
+  dF[4] = u_t[0] * (E + p) + U0 * (E_t + p_t) + T(g.pr_fix * g.cp) * p * u_t[0];
+  if (NEED_F) {
+    T T0 = p * ir;
+    T mu = T(g.mu_ref);
+    if (VAR_MU) mu = mu * pow(T0 / T(g.T_ref), T(g.mu_exp));
+    T s0 = mu * (T(2) * gu[0][0] + T(g.mub_m23) * theta);
+    T s1 = mu * (gu[0][1] + gu[1][0]);
+    T s2 = mu * (gu[0][2] + gu[2][0]);
+    T dTn = (gp[0] - T0 * D[0][0]) * ir;
+    F[0] = m0;
+    F[1] = m0 * U0 + p - s0;
+    F[2] = m0 * U1 - s1;
+    F[3] = m0 * U2 - s2;
+    F[4] = U0 * (E + p) - (U0 * s0 + U1 * s1 + U2 * s2) - T(g.cp * g.inv_pr) * mu * dTn;
+  }
+}
+
+}  // namespace hgks

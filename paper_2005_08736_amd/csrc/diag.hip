@@ -1,0 +1,196 @@
+// Global diagnostics of Sec. 3.1 and Sec. 3.4 in FP64 with a fixed reduction
+// order (each block owns a fixed set of cells; blocks are combined serially),
+// so repeated calls are bitwise identical.
+#include "internal.hpp"
+
+namespace hgks {
+
+constexpr int kDiagBlocks = 512;
+constexpr int kDiagThreads = 256;
+constexpr int kNDiag = 34;
+
+// accumulator slots (those with derived outputs are filled by the final kernel)
+enum {
+  A_TOT = 0, A_KE = 5, A_ENS = 6, A_EPS1 = 7, A_EPS2 = 8, A_EPS3 = 9, A_VAR = 10, A_U2 = 11,
+  A_MINR = 13, A_MINP = 14, A_EPSS = 16, A_EPSD = 17, A_PTH = 18, A_RHO = 19, A_G2 = 20, A_G3 = 23,
+  A_G4 = 26, A_C = 31, A_VOL = 32, A_MAXS = 33
+};
+
+__device__ __forceinline__ bool is_min_slot(int s) { return s == A_MINR || s == A_MINP; }
+__device__ __forceinline__ bool is_max_slot(int s) { return s == A_MAXS; }
+
+__device__ __forceinline__ double vel(const Geo& g, const double* q, long long i, int comp) {
+  return q[(long long)(1 + comp) * g.N + i] / q[i];
+}
+
+// pass 0: all sums; pass 1: sum (rho - mean)^2 V with the mean from pass 0
+__global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(Geo g, const double* __restrict__ q,
+                                                                    double* __restrict__ part, int pass,
+                                                                    const double* __restrict__ out) {
+  __shared__ double red[kDiagThreads];
+  double acc[kNDiag];
+#pragma unroll
+  for (int s = 0; s < kNDiag; ++s) acc[s] = is_min_slot(s) ? 1e300 : 0.0;
+  const double V = g.h[0] * g.h[1] * g.h[2];
+  const double mean_rho = pass == 1 ? out[19] : 0.0;
+  const double c6[3] = {45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0};  // antisymmetric weights at offsets 1, 2, 3
+  for (long long idx = (long long)blockIdx.x * kDiagThreads + threadIdx.x; idx < g.N;
+       idx += (long long)kDiagBlocks * kDiagThreads) {
+    double Q[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];
+    if (pass == 1) {
+      double dr = Q[0] - mean_rho;
+      acc[A_VAR] += dr * dr * V;
+      continue;
+    }
+    int c[3];
+    c[0] = int(idx % g.n[0]);
+    long long r = idx / g.n[0];
+    c[1] = int(r % g.n[1]);
+    c[2] = int(r / g.n[1]);
+    double ir = 1.0 / Q[0];
+    double U[3] = {Q[1] * ir, Q[2] * ir, Q[3] * ir};
+    double u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    double p = g.gm1 * (Q[4] - 0.5 * Q[0] * u2);
+    double T = p * ir;
+    double mu = g.mu_ref;
+    if (g.mu_exp != 0.0) mu *= pow(T / g.T_ref, g.mu_exp);
+    double cs = sqrt(g.gamma * p * ir);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[A_TOT + k] += Q[k] * V;
+    acc[A_KE] += 0.5 * Q[0] * u2 * V;
+    acc[A_RHO] += Q[0] * V;
+    acc[A_U2] += u2 / 3.0 * V;
+    acc[A_C] += cs * V;
+    acc[A_VOL] += V;
+    acc[A_MINR] = fmin(acc[A_MINR], Q[0]);
+    acc[A_MINP] = fmin(acc[A_MINP], p);
+    double sp = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sp = fmax(sp, (fabs(U[a]) + cs) * g.inv_h[a]);
+    acc[A_MAXS] = fmax(acc[A_MAXS], sp);
+    // velocity gradient gr[a][k] = dU_k/dx_a by the sixth-order central difference
+    double gr[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const long long base = idx - (long long)c[a] * g.stride[a];
+      double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int o = 1; o <= 3; ++o) {
+        long long ip = base + (long long)wrapi(c[a] + o, g.n[a]) * g.stride[a];
+        long long im = base + (long long)wrapi(c[a] - o, g.n[a]) * g.stride[a];
+        double irp = 1.0 / q[ip], irm = 1.0 / q[im];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          s[k] += c6[o - 1] * (q[(long long)(1 + k) * g.N + ip] * irp - q[(long long)(1 + k) * g.N + im] * irm);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gr[a][k] = s[k] * g.inv_h[a];
+    }
+    double wx = gr[1][2] - gr[2][1], wy = gr[2][0] - gr[0][2], wz = gr[0][1] - gr[1][0];
+    double w2 = wx * wx + wy * wy + wz * wz;
+    double th = gr[0][0] + gr[1][1] + gr[2][2];
+    double SS = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double S = 0.5 * (gr[a][k] + gr[k][a]) - (a == k ? th / 3.0 : 0.0);
+        SS += S * S;
+      }
+    double mub = (g.mub_m23 + 2.0 / 3.0) * mu;
+    acc[A_ENS] += 0.5 * Q[0] * w2 * V;
+    acc[A_EPS1] += 2.0 * mu * SS * V;
+    acc[A_EPS2] += mub * th * th * V;
+    acc[A_EPS3] += -p * th * V;
+    acc[A_EPSS] += mu * w2 * V;
+    acc[A_EPSD] += 4.0 / 3.0 * mu * th * th * V;
+    acc[A_PTH] += p * th * V;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double x = gr[a][a];
+      acc[A_G2 + a] += x * x * V;
+      acc[A_G3 + a] += x * x * x * V;
+      acc[A_G4 + a] += x * x * x * x * V;
+    }
+  }
+  // fixed-order tree reduction of each slot over the block
+  for (int s = 0; s < kNDiag; ++s) {
+    if (pass == 1 && s != A_VAR) continue;
+    red[threadIdx.x] = acc[s];
+    __syncthreads();
+    for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        double a = red[threadIdx.x], b = red[threadIdx.x + w];
+        red[threadIdx.x] = is_min_slot(s) ? fmin(a, b) : (is_max_slot(s) ? fmax(a, b) : a + b);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * kNDiag + s] = red[0];
+    __syncthreads();
+  }
+}
+
+// serial combination of the block partials and the derived quantities
+__global__ void diag_final_kernel(const double* __restrict__ part, double* __restrict__ out, int pass, double rho0) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc[kNDiag];
+  for (int s = 0; s < kNDiag; ++s) {
+    double v = is_min_slot(s) ? 1e300 : 0.0;
+    if (pass == 1 && s != A_VAR) continue;
+    for (int b = 0; b < kDiagBlocks; ++b) {
+      double x = part[(long long)b * kNDiag + s];
+      v = is_min_slot(s) ? fmin(v, x) : (is_max_slot(s) ? fmax(v, x) : v + x);
+    }
+    acc[s] = v;
+  }
+  if (pass == 1) {
+    out[10] = sqrt(acc[A_VAR] / out[32]);
+    return;
+  }
+  const double vol = acc[A_VOL];
+  for (int k = 0; k < 5; ++k) out[k] = acc[A_TOT + k];
+  out[5] = acc[A_KE] / (rho0 * vol);
+  out[6] = acc[A_ENS] / (rho0 * vol);
+  out[7] = acc[A_EPS1] / (rho0 * vol);
+  out[8] = acc[A_EPS2] / (rho0 * vol);
+  out[9] = acc[A_EPS3] / (rho0 * vol);
+  out[10] = 0.0;
+  out[11] = sqrt(acc[A_U2] / vol);
+  out[31] = acc[A_C] / vol;
+  out[12] = sqrt(3.0) * out[11] / out[31];
+  out[13] = acc[A_MINR];
+  out[14] = acc[A_MINP];
+  out[15] = acc[A_KE] / vol;
+  out[16] = acc[A_EPSS] / vol;
+  out[17] = acc[A_EPSD] / vol;
+  out[18] = acc[A_PTH] / vol;
+  out[19] = acc[A_RHO] / vol;
+  double Su = 0.0, Fu = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double m2 = acc[A_G2 + a] / vol, m3 = acc[A_G3 + a] / vol, m4 = acc[A_G4 + a] / vol;
+    out[20 + a] = m2;
+    out[23 + a] = m3;
+    out[26 + a] = m4;
+    if (m2 > 0.0) {
+      Su += m3 / pow(m2, 1.5);
+      Fu += m4 / (m2 * m2);
+    }
+  }
+  out[29] = Su;
+  out[30] = Fu;
+  out[32] = vol;
+  out[33] = acc[A_MAXS];
+}
+
+size_t diag_partial_doubles() { return size_t(kDiagBlocks) * kNDiag; }
+
+void launch_diagnostics(const Geo& g, const double* q, double* part, double* out, hipStream_t st) {
+  diag_partial_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part, 0, out);
+  diag_final_kernel<<<1, 64, 0, st>>>(part, out, 0, 1.0);
+  diag_partial_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part, 1, out);
+  diag_final_kernel<<<1, 64, 0, st>>>(part, out, 1, 1.0);
+}
+
+}  // namespace hgks

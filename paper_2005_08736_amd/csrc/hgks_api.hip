@@ -1,0 +1,337 @@
+// C ABI of libhgks (declared in include/hgks.h): parameter checks, workspace
+// carving and the sequencing of the two-stage step (Eq. (two-stage) of Sec. 2.1)
+// on the caller's stream.  The library allocates no device memory.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/hgks.h"
+#include "internal.hpp"
+
+using namespace hgks;
+
+struct hgks_handle {
+  hgks_params p;
+  Geo geo;
+  double* q;            // caller's state
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  // workspace carve
+  Ctrl* ctrl;
+  double* qs;           // Q* / Q^{n+1} ping-pong partner of q
+  double* rr;           // R = Q^n + dt L + dt^2/6 dL
+  double* fl;           // face fluxes of the three directions [3][10][N]
+  double* diag_part;    // block partials of the diagnostics
+  double* diag_out;     // derived diagnostics [HGKS_NDIAG]
+  double* speed_part;   // block maxima of the CFL speed
+  long long steps_done; // steps advanced over the handle's lifetime
+  int failed_step;
+  // optional per-kernel timing
+  bool profiling;
+  std::vector<hipEvent_t> events;          // pool, two per recorded launch
+  std::vector<int> pending_class;          // class of each recorded launch in this call
+  double prof_ms[HGKS_KCLASS_COUNT];
+  long long prof_count[HGKS_KCLASS_COUNT];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, total;
+};
+
+Layout layout_for(long long N) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.ctrl = take(sizeof(Ctrl));
+  L.qs = take(sizeof(double) * 5 * N);
+  L.rr = take(sizeof(double) * 5 * N);
+  L.fl = take(sizeof(double) * 30 * N);
+  L.diag_part = take(sizeof(double) * diag_partial_doubles());
+  L.diag_out = take(sizeof(double) * 64);
+  L.speed_part = take(sizeof(double) * size_t((N + 255) / 256));
+  L.total = off;
+  return L;
+}
+
+int validate(const hgks_params* p) {
+  if (!p) return HGKS_E_INVALID_ARG;
+  const int minp = 6;
+  if (p->nx < minp || p->ny < minp || p->nz < minp) return HGKS_E_INVALID_ARG;
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0)) return HGKS_E_INVALID_ARG;
+  if (!(p->gamma > 1.0) || !(p->prandtl > 0.0) || !(p->mu_ref >= 0.0) || !(p->cfl > 0.0)) return HGKS_E_INVALID_ARG;
+  if (p->mu_exp != 0.0 && !(p->T_ref > 0.0)) return HGKS_E_INVALID_ARG;
+  if (p->mode != HGKS_MODE_SMOOTH && p->mode != HGKS_MODE_WENOZ) return HGKS_E_INVALID_ARG;
+  if (p->precision != HGKS_PREC_F64 && p->precision != HGKS_PREC_F32FLUX) return HGKS_E_INVALID_ARG;
+  if (p->bc_y != HGKS_BC_PERIODIC && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_INVALID_ARG;
+  long long N = (long long)p->nx * p->ny * p->nz;
+  if (N > (1LL << 31) - 1) return HGKS_E_INVALID_ARG;  // 32-bit cell counts in the launch grids
+  // implemented so far: smooth mode, FP64, periodic boxes
+  if (p->mode != HGKS_MODE_SMOOTH || p->precision != HGKS_PREC_F64 || p->bc_y != HGKS_BC_PERIODIC ||
+      p->stretch_b != 0.0 || p->body_force_x != 0.0)
+    return HGKS_E_UNSUPPORTED;
+  return HGKS_OK;
+}
+
+Geo make_geo(const hgks_params* p) {
+  Geo g;
+  g.n[0] = p->nx;
+  g.n[1] = p->ny;
+  g.n[2] = p->nz;
+  g.N = (long long)p->nx * p->ny * p->nz;
+  g.stride[0] = 1;
+  g.stride[1] = p->nx;
+  g.stride[2] = (long long)p->nx * p->ny;
+  g.h[0] = p->lx / p->nx;
+  g.h[1] = p->ly / p->ny;
+  g.h[2] = p->lz / p->nz;
+  for (int a = 0; a < 3; ++a) g.inv_h[a] = 1.0 / g.h[a];
+  g.gamma = p->gamma;
+  g.gm1 = p->gamma - 1.0;
+  g.inv_gm1 = 1.0 / g.gm1;
+  g.cp = p->gamma / (p->gamma - 1.0);
+  g.inv_pr = 1.0 / p->prandtl;
+  g.pr_fix = 1.0 / p->prandtl - 1.0;
+  g.K = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
+  g.mub_m23 = 2.0 * g.K / (3.0 * (g.K + 3.0)) - 2.0 / 3.0;
+  g.mu_ref = p->mu_ref;
+  g.T_ref = p->T_ref;
+  g.mu_exp = p->mu_exp;
+  g.cfl = p->cfl;
+  return g;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? HGKS_OK : HGKS_E_DEVICE; }
+
+// Timing brackets (no-ops unless profiling is enabled).
+bool prof_begin(hgks_handle* h, int cls) {
+  if (!h->profiling) return false;
+  size_t k = h->pending_class.size();
+  while (h->events.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    h->events.push_back(e);
+  }
+  h->pending_class.push_back(cls);
+  (void)hipEventRecord(h->events[2 * k], h->stream);
+  return true;
+}
+void prof_end(hgks_handle* h, bool on) {
+  if (on) (void)hipEventRecord(h->events[2 * (h->pending_class.size() - 1) + 1], h->stream);
+}
+// after a stream synchronization: fold the recorded launches into the totals
+void prof_collect(hgks_handle* h) {
+  for (size_t k = 0; k < h->pending_class.size(); ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]) == hipSuccess) {
+      h->prof_ms[h->pending_class[k]] += ms;
+      h->prof_count[h->pending_class[k]] += 1;
+    }
+  }
+  h->pending_class.clear();
+}
+
+// fluxes of all three directions of state src into h->fl (stage 2: time derivative only)
+void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop) {
+  for (int d = 0; d < 3; ++d) {
+    bool on = prof_begin(h, stage2 ? HGKS_KCLASS_FLUX_STAGE2 : HGKS_KCLASS_FLUX_STAGE1);
+    launch_flux_fused(h->geo, d, stage2, src, h->fl + (size_t)d * 10 * h->geo.N, stop, h->stream);
+    prof_end(h, on);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hgks_workspace_bytes(const hgks_params* p) {
+  int v = validate(p);
+  if (v != HGKS_OK) return 0;
+  return layout_for((long long)p->nx * p->ny * p->nz).total;
+}
+
+int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes, void* hip_stream,
+              hgks_handle** out) {
+  if (!out) return HGKS_E_INVALID_ARG;
+  *out = nullptr;
+  int v = validate(p);
+  if (v != HGKS_OK) return v;
+  if (!q) return HGKS_E_INVALID_ARG;
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  Layout L = layout_for(N);
+  if (!workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+    return HGKS_E_WORKSPACE;
+  hgks_handle* h = new (std::nothrow) hgks_handle;
+  if (!h) return HGKS_E_INVALID_ARG;
+  h->p = *p;
+  h->geo = make_geo(p);
+  h->q = q;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(workspace);
+  h->ws_bytes = ws_bytes;
+  h->ctrl = reinterpret_cast<Ctrl*>(h->ws + L.ctrl);
+  h->qs = reinterpret_cast<double*>(h->ws + L.qs);
+  h->rr = reinterpret_cast<double*>(h->ws + L.rr);
+  h->fl = reinterpret_cast<double*>(h->ws + L.fl);
+  h->diag_part = reinterpret_cast<double*>(h->ws + L.diag_part);
+  h->diag_out = reinterpret_cast<double*>(h->ws + L.diag_out);
+  h->speed_part = reinterpret_cast<double*>(h->ws + L.speed_part);
+  h->steps_done = 0;
+  h->failed_step = -1;
+  h->profiling = false;
+  for (int k = 0; k < HGKS_KCLASS_COUNT; ++k) { h->prof_ms[k] = 0.0; h->prof_count[k] = 0; }
+  launch_reset_ctrl(h->ctrl, h->stream);
+  if (hipGetLastError() != hipSuccess) {
+    delete h;
+    return HGKS_E_DEVICE;
+  }
+  *out = h;
+  return HGKS_OK;
+}
+
+int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
+  if (!h || nsteps < 0) return HGKS_E_INVALID_ARG;
+  if (nsteps == 0) return HGKS_OK;
+  if (!(dt > 0.0)) dt = 0.0;
+  const Geo& g = h->geo;
+  hipStream_t st = h->stream;
+  const long long s0 = h->steps_done;
+  int done = 0;
+  while (done < nsteps) {
+    const int chunk = (nsteps - done) < kDtHist ? (nsteps - done) : kDtHist;
+    launch_reset_ctrl(h->ctrl, st);
+    launch_check_state(g, h->q, h->ctrl, h->speed_part, int(s0 + done) - 1, st);
+    double* cur = h->q;
+    double* other = h->qs;
+    for (int s = 0; s < chunk; ++s) {
+      const int step = int(s0 + done + s);
+      launch_dt(g, h->speed_part, h->ctrl, dt, s, st);
+      all_fluxes(h, cur, false, &h->ctrl->flag);
+      bool on = prof_begin(h, HGKS_KCLASS_STAGE1);
+      launch_stage1(g, cur, h->fl, other, h->rr, h->ctrl, step, st);
+      prof_end(h, on);
+      all_fluxes(h, other, true, &h->ctrl->flag);
+      on = prof_begin(h, HGKS_KCLASS_STAGE2);
+      launch_stage2(g, h->rr, h->fl, other, h->ctrl, h->speed_part, step, st);
+      prof_end(h, on);
+      double* t = cur;
+      cur = other;
+      other = t;
+    }
+    if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+    Ctrl host;
+    if (hipMemcpyAsync(&host, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return HGKS_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return HGKS_E_DEVICE;
+    prof_collect(h);
+    if (host.flag) {
+      // the last good state is the one the failing step started from
+      const long long local = (long long)host.fail_step - (s0 + done);
+      if (local >= 0 && (local & 1)) {
+        launch_copy(h->qs, h->q, 5 * g.N, st);
+        if (hipStreamSynchronize(st) != hipSuccess) return HGKS_E_DEVICE;
+      }
+      if (dt_taken && local > 0)
+        for (long long s = 0; s < local; ++s) dt_taken[done + s] = host.dt_hist[s];
+      h->failed_step = host.fail_step;
+      h->steps_done = local > 0 ? s0 + done + local : s0 + done;
+      return HGKS_E_NONPHYSICAL;
+    }
+    if (cur != h->q) launch_copy(cur, h->q, 5 * g.N, st);
+    if (dt_taken)
+      for (int s = 0; s < chunk; ++s) dt_taken[done + s] = host.dt_hist[s];
+    done += chunk;
+  }
+  h->steps_done = s0 + nsteps;
+  if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+  return hip_status(hipStreamSynchronize(st));
+}
+
+int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, double* dL) {
+  (void)dt;
+  if (!h || !q_in || !L || !dL) return HGKS_E_INVALID_ARG;
+  all_fluxes(h, q_in, false, &h->ctrl->zero);
+  launch_operator(h->geo, h->fl, L, dL, h->stream);
+  return hip_status(hipGetLastError());
+}
+
+int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF) {
+  (void)dt;
+  if (!h || !q_in || !F || !dF || dir < 0 || dir > 2) return HGKS_E_INVALID_ARG;
+  const Geo& g = h->geo;
+  double* fl = h->fl + (size_t)dir * 10 * g.N;
+  launch_flux_fused(g, dir, false, q_in, fl, &h->ctrl->zero, h->stream);
+  if (hipMemcpyAsync(F, fl, sizeof(double) * 5 * g.N, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(dF, fl + 5 * g.N, sizeof(double) * 5 * g.N, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  return hip_status(hipGetLastError());
+}
+
+int hgks_diagnostics(hgks_handle* h, double* out) {
+  if (!h || !out) return HGKS_E_INVALID_ARG;
+  launch_diagnostics(h->geo, h->q, h->diag_part, h->diag_out, h->stream);
+  if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(out, h->diag_out, sizeof(double) * HGKS_NDIAG, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  return hip_status(hipStreamSynchronize(h->stream));
+}
+
+int hgks_profile_enable(hgks_handle* h, int enable) {
+  if (!h) return HGKS_E_INVALID_ARG;
+  if (!enable) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return HGKS_E_DEVICE;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    h->pending_class.clear();
+  }
+  h->profiling = enable != 0;
+  return HGKS_OK;
+}
+
+int hgks_profile_read(hgks_handle* h, double* ms, int64_t* counts, int n) {
+  if (!h || !ms || !counts || n < 0 || n > HGKS_KCLASS_COUNT) return HGKS_E_INVALID_ARG;
+  for (int k = 0; k < n; ++k) {
+    ms[k] = h->prof_ms[k];
+    counts[k] = h->prof_count[k];
+  }
+  for (int k = 0; k < HGKS_KCLASS_COUNT; ++k) { h->prof_ms[k] = 0.0; h->prof_count[k] = 0; }
+  return HGKS_OK;
+}
+
+int hgks_failed_step(const hgks_handle* h) { return h ? h->failed_step : -1; }
+
+void hgks_destroy(hgks_handle* h) {
+  if (!h) return;
+  if (!h->events.empty()) {
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  }
+  delete h;
+}
+
+const char* hgks_strerror(int status) {
+  switch (status) {
+    case HGKS_OK: return "ok";
+    case HGKS_E_INVALID_ARG: return "invalid argument";
+    case HGKS_E_DEVICE: return "HIP runtime error";
+    case HGKS_E_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+    case HGKS_E_UNSUPPORTED: return "unsupported parameter combination";
+    case HGKS_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

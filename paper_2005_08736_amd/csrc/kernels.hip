@@ -1,0 +1,219 @@
+// Stage kernels of the HGKS update for gfx950: the divergence of the face fluxes
+// (Eq. (finite)), the two-stage formula of Eq. (two-stage), the CFL speed
+// reduction and the physicality check of each new state.  The face fluxes come
+// from flux_fused.hip.
+#include "internal.hpp"
+
+namespace hgks {
+
+template <int DIR>
+__device__ __forceinline__ void cell_coords(const Geo& g, long long idx, int* c) {
+  c[0] = int(idx % g.n[0]);
+  long long r = idx / g.n[0];
+  c[1] = int(r % g.n[1]);
+  c[2] = int(r / g.n[1]);
+}
+
+// ---------------------------------------------------------------------------
+// Stage updates.
+// ---------------------------------------------------------------------------
+// max over axes of (|U_d| + c)/h_d, and whether the state is physical
+__device__ __forceinline__ double cell_speed(const Geo& g, const double* Q, bool& ok) {
+  double ir = 1.0 / Q[0];
+  double U = Q[1] * ir, V = Q[2] * ir, W = Q[3] * ir;
+  double p = g.gm1 * (Q[4] - 0.5 * Q[0] * (U * U + V * V + W * W));
+  ok = (Q[0] > 0.0) && (p > 0.0) && isfinite(p) && isfinite(Q[0]);
+  double c = sqrt(g.gamma * p * ir);
+  double s = (fabs(U) + c) * g.inv_h[0];
+  s = fmax(s, (fabs(V) + c) * g.inv_h[1]);
+  s = fmax(s, (fabs(W) + c) * g.inv_h[2]);
+  return s;
+}
+
+// block maximum of v (256 threads) written to part[blockIdx.x]
+__device__ __forceinline__ void block_max_speed(double v, double* part) {
+  __shared__ double wmax[4];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+}
+
+__device__ __forceinline__ void divergence(const Geo& g, const double* fl, long long idx, const int* c, int k,
+                                           double* L, double* dL) {
+  double l = 0.0, dl = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double* F = fl + (long long)d * 10 * g.N;
+    long long lo = c[d] == 0 ? idx + (long long)(g.n[d] - 1) * g.stride[d] : idx - g.stride[d];
+    if (L) l -= (F[(long long)k * g.N + idx] - F[(long long)k * g.N + lo]) * g.inv_h[d];
+    dl -= (F[(long long)(5 + k) * g.N + idx] - F[(long long)(5 + k) * g.N + lo]) * g.inv_h[d];
+  }
+  if (L) *L = l;
+  *dL = dl;
+}
+
+// Time step of the step about to start: the maximum of the block maxima of the
+// CFL speed left by the previous stage-2 (or state-check) kernel; one block.
+__global__ void __launch_bounds__(1024) dt_kernel(Geo g, const double* __restrict__ part, int nparts, Ctrl* ctrl,
+                                                  double dt_fixed, int hist) {
+  __shared__ double wmax[16];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 1024) v = fmax(v, part[i]);
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < 16; ++w) m = fmax(m, wmax[w]);
+    double dt = dt_fixed > 0.0 ? dt_fixed : g.cfl / m;
+    ctrl->maxspeed = m;
+    ctrl->dt = dt;
+    ctrl->dt_hist[hist] = dt;
+  }
+}
+
+// Q* = Q^n + dt/2 L + dt^2/8 dL ; R = Q^n + dt L + dt^2/6 dL
+__global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __restrict__ qn, const double* __restrict__ fl,
+                                                     double* __restrict__ qs, double* __restrict__ rr, Ctrl* ctrl,
+                                                     int step) {
+  if (ctrl->flag) return;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dt = ctrl->dt;
+  if (idx >= g.N) return;
+  int c[3];
+  cell_coords<0>(g, idx, c);
+  double Qs[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double L, dL;
+    divergence(g, fl, idx, c, k, &L, &dL);
+    double q0 = qn[(long long)k * g.N + idx];
+    Qs[k] = q0 + 0.5 * dt * L + 0.125 * dt * dt * dL;
+    qs[(long long)k * g.N + idx] = Qs[k];
+    rr[(long long)k * g.N + idx] = q0 + dt * L + (dt * dt / 6.0) * dL;
+  }
+  bool ok;
+  (void)cell_speed(g, Qs, ok);
+  if (!ok) {
+    ctrl->fail_step = step;
+    ctrl->flag = 1;
+  }
+}
+
+// Q^{n+1} = R + dt^2/3 dL(Q*); block maxima of the next step's CFL speed.
+__global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __restrict__ rr, const double* __restrict__ fl,
+                                                     double* __restrict__ qout, Ctrl* ctrl, double* __restrict__ part,
+                                                     int step) {
+  if (ctrl->flag) return;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dt = ctrl->dt;
+  double speed = 0.0;
+  if (idx < g.N) {
+    int c[3];
+    cell_coords<0>(g, idx, c);
+    double Qn[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double dL;
+      divergence(g, fl, idx, c, k, nullptr, &dL);
+      Qn[k] = rr[(long long)k * g.N + idx] + (dt * dt / 3.0) * dL;
+      qout[(long long)k * g.N + idx] = Qn[k];
+    }
+    bool ok;
+    speed = cell_speed(g, Qn, ok);
+    if (!ok) {
+      ctrl->fail_step = step;
+      ctrl->flag = 1;
+    }
+  }
+  block_max_speed(speed, part);
+}
+
+// CFL speed and physicality of the state at the start of a call.
+__global__ void __launch_bounds__(256) check_state_kernel(Geo g, const double* __restrict__ q, Ctrl* ctrl,
+                                                          double* __restrict__ part, int step) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double speed = 0.0;
+  if (idx < g.N) {
+    double Q[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];
+    bool ok;
+    speed = cell_speed(g, Q, ok);
+    if (!ok) {
+      ctrl->fail_step = step;
+      ctrl->flag = 1;
+    }
+  }
+  block_max_speed(speed, part);
+}
+
+__global__ void reset_ctrl_kernel(Ctrl* ctrl) {
+  ctrl->dt = 0.0;
+  ctrl->maxspeed = 0.0;
+  ctrl->flag = 0;
+  ctrl->fail_step = -1;
+  ctrl->zero = 0;
+}
+
+// L and dL of Eq. (finite) from the face fluxes (parity entry point).
+__global__ void __launch_bounds__(256) operator_kernel(Geo g, const double* __restrict__ fl, double* __restrict__ L,
+                                                       double* __restrict__ dL) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.N) return;
+  int c[3];
+  cell_coords<0>(g, idx, c);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double l, dl;
+    divergence(g, fl, idx, c, k, &l, &dl);
+    L[(long long)k * g.N + idx] = l;
+    dL[(long long)k * g.N + idx] = dl;
+  }
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(const double* __restrict__ src, double* __restrict__ dst, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(long long n) { return unsigned((n + 255) / 256); }
+
+void launch_dt(const Geo& g, const double* part, Ctrl* ctrl, double dt_fixed, int hist, hipStream_t st) {
+  dt_kernel<<<1, 1024, 0, st>>>(g, part, int(blocks_for(g.N)), ctrl, dt_fixed, hist);
+}
+
+void launch_stage1(const Geo& g, const double* qn, const double* fl, double* qs, double* rr, Ctrl* ctrl, int step,
+                   hipStream_t st) {
+  stage1_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, qn, fl, qs, rr, ctrl, step);
+}
+
+void launch_stage2(const Geo& g, const double* rr, const double* fl, double* qout, Ctrl* ctrl, double* part, int step,
+                   hipStream_t st) {
+  stage2_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qout, ctrl, part, step);
+}
+
+void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st) {
+  check_state_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, q, ctrl, part, step);
+}
+
+size_t speed_partials(const Geo& g) { return size_t(blocks_for(g.N)); }
+
+void launch_reset_ctrl(Ctrl* ctrl, hipStream_t st) { reset_ctrl_kernel<<<1, 1, 0, st>>>(ctrl); }
+
+void launch_operator(const Geo& g, const double* fl, double* L, double* dL, hipStream_t st) {
+  operator_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, fl, L, dL);
+}
+
+void launch_copy(const double* src, double* dst, long long n, hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  copy_kernel<<<unsigned(b), 256, 0, st>>>(src, dst, n);
+}
+
+}  // namespace hgks

@@ -1,0 +1,203 @@
+"""Python binding of libhgks (the C ABI of include/hgks.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels of
+``libhgks.so``.  PyTorch provides the device memory (state, workspace, outputs)
+and the stream.  Importing works without a GPU; creating a :class:`Solver` needs
+the built library and a ROCm device, and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# HGKS_LIB may point at another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("HGKS_LIB", os.path.join(HERE, "libhgks.so"))
+
+HGKS_OK = 0
+HGKS_E_INVALID_ARG = -1
+HGKS_E_DEVICE = -2
+HGKS_E_NONPHYSICAL = -3
+HGKS_E_UNSUPPORTED = -4
+HGKS_E_WORKSPACE = -5
+HGKS_NDIAG = 34
+MODE_SMOOTH, MODE_WENOZ = 0, 1
+PREC_F64, PREC_F32FLUX = 0, 1
+
+DIAG_NAMES = [
+    "mass", "mom_x", "mom_y", "mom_z", "energy", "E_k", "zeta", "eps1", "eps2", "eps3",
+    "rho_rms", "u_rms", "Ma_t", "min_rho", "min_p", "K", "eps_s", "eps_d", "p_theta", "rho_mean",
+    "dudx2", "dvdy2", "dwdz2", "dudx3", "dvdy3", "dwdz3", "dudx4", "dvdy4", "dwdz4",
+    "S_u", "F_u", "c_mean", "volume", "max_speed",
+]
+
+EXPORTED = [
+    "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
+    "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
+    "hgks_profile_enable", "hgks_profile_read",
+]
+KCLASS_NAMES = ["face_field", "flux_stage1", "flux_stage2", "stage1", "stage2"]
+
+
+class HgksParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+        ("bc_y", ctypes.c_int32), ("stretch_b", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("mu_exp", ctypes.c_double),
+        ("mode", ctypes.c_int32), ("cfl", ctypes.c_double),
+        ("c_art", ctypes.c_double), ("weno_eps", ctypes.c_double), ("weno_p", ctypes.c_int32),
+        ("T_wall", ctypes.c_double), ("body_force_x", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class HgksError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+_lib = None
+
+
+def load():
+    """Load libhgks.so (built in-tree by ``paper_2005_08736_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_08736_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(HgksParams)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    D = ctypes.POINTER(ctypes.c_double)
+    L.hgks_workspace_bytes.restype = sz
+    L.hgks_workspace_bytes.argtypes = [P]
+    L.hgks_init.restype = ctypes.c_int
+    L.hgks_init.argtypes = [P, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    L.hgks_step.restype = ctypes.c_int
+    L.hgks_step.argtypes = [vp, i32, dbl, D]
+    L.hgks_operator.restype = ctypes.c_int
+    L.hgks_operator.argtypes = [vp, vp, dbl, vp, vp]
+    L.hgks_face_flux.restype = ctypes.c_int
+    L.hgks_face_flux.argtypes = [vp, i32, vp, dbl, vp, vp]
+    L.hgks_diagnostics.restype = ctypes.c_int
+    L.hgks_diagnostics.argtypes = [vp, D]
+    L.hgks_failed_step.restype = ctypes.c_int
+    L.hgks_failed_step.argtypes = [vp]
+    L.hgks_destroy.restype = None
+    L.hgks_destroy.argtypes = [vp]
+    L.hgks_profile_enable.restype = ctypes.c_int
+    L.hgks_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.hgks_profile_read.restype = ctypes.c_int
+    L.hgks_profile_read.argtypes = [vp, D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    L.hgks_strerror.restype = ctypes.c_char_p
+    L.hgks_strerror.argtypes = [ctypes.c_int]
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load().hgks_strerror(int(status)).decode()
+
+
+def make_params(d: dict) -> HgksParams:
+    p = HgksParams()
+    for name, _ in HgksParams._fields_:
+        setattr(p, name, d.get(name, 0))
+    return p
+
+
+def workspace_bytes(params: dict) -> int:
+    return int(load().hgks_workspace_bytes(ctypes.byref(make_params(params))))
+
+
+def _check(status: int, what: str):
+    if status != HGKS_OK:
+        raise HgksError(status, what)
+
+
+class Solver:
+    """One HGKS state on one device: binds a caller-owned CUDA/HIP float64 tensor
+    ``q`` of shape [5, nz, ny, nx] (updated in place) and a workspace tensor."""
+
+    def __init__(self, params: dict, q: torch.Tensor, stream: torch.cuda.Stream | None = None):
+        L = load()
+        if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous()):
+            raise ValueError("q must be a contiguous float64 device tensor")
+        if tuple(q.shape) != (5, params["nz"], params["ny"], params["nx"]):
+            raise ValueError(f"q has shape {tuple(q.shape)}, expected (5, nz, ny, nx)")
+        self.params = dict(params)
+        self._p = make_params(params)
+        nbytes = int(L.hgks_workspace_bytes(ctypes.byref(self._p)))
+        if nbytes == 0:
+            raise HgksError(HGKS_E_INVALID_ARG, "hgks_workspace_bytes")
+        self.q = q
+        self.stream = stream if stream is not None else torch.cuda.current_stream(q.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=q.device)
+        h = ctypes.c_void_p()
+        _check(L.hgks_init(ctypes.byref(self._p), ctypes.c_void_p(q.data_ptr()),
+                           ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hgks_init")
+        self._h = h
+
+    def step(self, nsteps: int = 1, dt: float = 0.0, return_dt: bool = False):
+        """Advance nsteps steps (dt <= 0: CFL time step); optionally return the dts."""
+        buf = (ctypes.c_double * max(int(nsteps), 1))()
+        st = load().hgks_step(self._h, int(nsteps), float(dt), buf if return_dt else None)
+        if st != HGKS_OK:
+            raise HgksError(st, "hgks_step")
+        return [buf[i] for i in range(int(nsteps))] if return_dt else None
+
+    def step_status(self, nsteps: int = 1, dt: float = 0.0) -> int:
+        return int(load().hgks_step(self._h, int(nsteps), float(dt), None))
+
+    def failed_step(self) -> int:
+        return int(load().hgks_failed_step(self._h))
+
+    def operator(self, q_in: torch.Tensor | None = None, dt: float = 0.0):
+        q_in = self.q if q_in is None else q_in
+        L = torch.empty_like(self.q)
+        dL = torch.empty_like(self.q)
+        _check(load().hgks_operator(self._h, ctypes.c_void_p(q_in.data_ptr()), float(dt),
+                                    ctypes.c_void_p(L.data_ptr()), ctypes.c_void_p(dL.data_ptr())), "hgks_operator")
+        return L, dL
+
+    def face_flux(self, direction: int, q_in: torch.Tensor | None = None, dt: float = 0.0):
+        q_in = self.q if q_in is None else q_in
+        F = torch.empty_like(self.q)
+        dF = torch.empty_like(self.q)
+        _check(load().hgks_face_flux(self._h, int(direction), ctypes.c_void_p(q_in.data_ptr()), float(dt),
+                                     ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(dF.data_ptr())),
+               "hgks_face_flux")
+        return F, dF
+
+    def diagnostics(self) -> dict:
+        out = (ctypes.c_double * HGKS_NDIAG)()
+        _check(load().hgks_diagnostics(self._h, out), "hgks_diagnostics")
+        return dict(zip(DIAG_NAMES, list(out)))
+
+    def profile(self, enable: bool = True):
+        _check(load().hgks_profile_enable(self._h, int(bool(enable))), "hgks_profile_enable")
+
+    def profile_read(self) -> dict:
+        n = len(KCLASS_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(load().hgks_profile_read(self._h, ms, cnt, n), "hgks_profile_read")
+        return {KCLASS_NAMES[k]: (ms[k], int(cnt[k])) for k in range(n)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hgks_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,61 @@
+"""CPU checks of the C ABI: the HIP library loads and exports every function the
+header declares; parameter validation that runs without a device."""
+import os
+import re
+
+import pytest
+
+from paper_2005_08736_amd import cases, hgks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(hgks_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hgks.load()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(hgks.EXPORTED) <= set(names)
+
+
+def test_workspace_size_and_validation():
+    p = cases.tgv_params(32)
+    ws = hgks.workspace_bytes(p)
+    assert ws >= 40 * 8 * 32 ** 3
+    assert ws % 256 == 0
+    for bad in (dict(nx=5), dict(gamma=1.0), dict(cfl=0.0), dict(prandtl=-1.0), dict(mode=7), dict(mu_ref=-1.0)):
+        q = dict(p)
+        q.update(bad)
+        assert hgks.workspace_bytes(q) == 0, bad
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert hgks.strerror(code) != "unknown status"
+
+
+def test_params_struct_matches_header_field_order():
+    src = open(os.path.join(ROOT, "include", "hgks.h")).read()
+    body = src[src.index("typedef struct {"):src.index("} hgks_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    decl = []
+    for line in body.splitlines()[1:]:
+        line = line.strip().rstrip(";")
+        if not line:
+            continue
+        typ, rest = line.split(None, 1)
+        decl += [(n.strip(), typ) for n in rest.split(",")]
+    fields = [(n, "int32_t" if t.__name__ == "c_int" else "double") for n, t in hgks.HgksParams._fields_]
+    assert [d[0] for d in decl] == [f[0] for f in fields]
+    assert [d[1] for d in decl] == [f[1] for f in fields]
