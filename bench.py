@@ -31,11 +31,13 @@ PAPER_MCUPS_256 = 256 ** 3 / 9.09 / 1e6
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops of one face in the stage-1 flux kernel (tangential
+# Algorithmic FP64 flops of one face in the stage-1 flux kernel: normal
+# reconstruction + compatibility state + normal derivative (639) and tangential
 # reconstruction to four Gauss points + four gas-kinetic flux evaluations + face
-# average), counted as executed FP64 VALU operations per face (FMA = 2) by
-# rocprofv3 counters on this kernel source; see profiles/.
-FLUX_STAGE1_FLOPS_PER_FACE = None
+# average (2320), each face evaluated once.  Counted as executed FP64 VALU
+# operations (FMA = 2, SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / faces) by rocprofv3
+# on the unfused kernels, where every face was computed exactly once.
+FLUX_STAGE1_FLOPS_PER_FACE = 639 + 2320
 # HBM bytes per face of the stage-1 flux kernel from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE, scaled by the copy-kernel calibration factor; valid only for the
 # kernel source with this digest.
@@ -45,7 +47,7 @@ FLUX_COUNTERS_SOURCE_DIGEST = None
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "device_common.hpp"):
+    for name in ("flux_fused.hip", "device_common.hpp"):
         with open(os.path.join(ROOT, "paper_2005_08736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -100,49 +102,67 @@ def main():
         raise RuntimeError("bench.py needs a ROCm device")
     dev = torch.device("cuda:0")
     n = args.n
-    p = cases.tgv_params(n)
-    log(f"[bench] building Taylor-Green {n}^3 initial state")
-    q = torch.from_numpy(cases.tgv_state(n)).to(dev)
-    s = hgks.Solver(p, q)
-    log(f"[bench] warmup {args.warmup} steps")
-    if args.warmup:
-        s.step(args.warmup)
-    s.profile(True)
-    s.profile_read()  # reset
-    torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} steps")
-    t0 = time.perf_counter()
-    dts = s.step(args.steps, return_dt=True)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = s.profile_read()
-    s.profile(False)
     N = n ** 3
-    value = N * args.steps / el / 1e6
-    ms_per_step = el / args.steps * 1e3
-    log(f"[bench] {ms_per_step:.3f} ms/step, {value:.1f} Mcell-updates/s, dt={dts[0]:.4e}")
-    for k, (ms, cnt) in prof.items():
-        log(f"[bench]   {k:12s} {ms:9.3f} ms total over {cnt} launches ({ms / max(cnt, 1):.4f} ms avg)")
+    log(f"[bench] building Taylor-Green {n}^3 initial state")
+    q_init = cases.tgv_state(n)
+
+    def run(precision):
+        p = dict(cases.tgv_params(n))
+        p["precision"] = precision
+        q = torch.from_numpy(q_init).to(dev)
+        s = hgks.Solver(p, q)
+        log(f"[bench] precision={precision}: warmup {args.warmup} steps")
+        if args.warmup:
+            s.step(args.warmup)
+        s.profile(True)
+        s.profile_read()
+        torch.cuda.synchronize()
+        log(f"[bench] precision={precision}: timing {args.steps} steps")
+        t0 = time.perf_counter()
+        dts = s.step(args.steps, return_dt=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = s.profile_read()
+        s.profile(False)
+        value = N * args.steps / el / 1e6
+        log(f"[bench]   {el / args.steps * 1e3:.3f} ms/step, {value:.1f} Mcell-updates/s, dt={dts[0]:.4e}")
+        for k, (ms, cnt) in prof.items():
+            if cnt:
+                log(f"[bench]   {k:12s} {ms:9.3f} ms over {cnt} launches ({ms / cnt:.4f} ms avg)")
+        return dict(value=value, ms=el / args.steps * 1e3, prof=prof, dts=dts, solver=s, q=q)
+
+    r64 = run(hgks.PREC_F64)
+    r32 = run(hgks.PREC_F32FLUX)
+    value = r64["value"]
+    ms_per_step = r64["ms"]
+    dts = r64["dts"]
+    # FP32 form against the FP64 path after the same number of steps
+    a, b = r32["q"].cpu().numpy(), r64["q"].cpu().numpy()
+    mom = float(np.sqrt(np.sum(b[1:4] ** 2)))
+    rel = [float(np.linalg.norm(a[k] - b[k])) / (mom if 1 <= k <= 3 else float(np.linalg.norm(b[k])))
+           for k in range(5)]
+    fp32 = {"value": r32["value"], "ms_per_step": r32["ms"], "speedup_vs_fp64": r32["value"] / value,
+            "rel_l2_vs_fp64_after_steps": max(rel), "rel_l2_per_field": rel,
+            "steps_compared": args.warmup + args.steps}
+    log(f"[bench] FP32 form: {fp32['speedup_vs_fp64']:.2f}x, rel L2 vs FP64 {max(rel):.2e}")
+    prof = r64["prof"]
     ms_flux, cnt_flux = prof["flux_stage1"]
     avg_flux_s = ms_flux / max(cnt_flux, 1) / 1e3
-    if FLUX_STAGE1_FLOPS_PER_FACE is not None:
-        achieved = FLUX_STAGE1_FLOPS_PER_FACE * N / avg_flux_s / 1e12
-    else:
-        achieved = None
+    achieved = FLUX_STAGE1_FLOPS_PER_FACE * N / avg_flux_s / 1e12
     traffic = None
     if FLUX_STAGE1_HBM_BYTES_PER_FACE is not None and FLUX_COUNTERS_SOURCE_DIGEST == kernel_source_digest():
         traffic = FLUX_STAGE1_HBM_BYTES_PER_FACE * N
     roofline = {
         "bound": "alu",
-        "kernel": "face_flux (stage 1)",
+        "kernel": "flux_fused (stage 1, FP64)",
         "achieved": achieved,
         "peak": PEAK_FP64_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": (achieved / PEAK_FP64_VECTOR_TFLOPS) if achieved is not None else None,
+        "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
         "traffic": traffic,
         "avg_launch_ms": avg_flux_s * 1e3,
     }
-    d = s.diagnostics()
+    d = r64["solver"].diagnostics()
     log(f"[bench] after {args.warmup + args.steps} steps: E_k={d['E_k']:.8f} min_p={d['min_p']:.6f}")
     cpu = None
     if not args.no_cpu:
@@ -165,6 +185,7 @@ def main():
         "config": {"workload": f"taylor_green_{n}^3_fp64_smooth", "cells": N, "cfl": 0.4, "dt": dts[0],
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "fp32_form": fp32,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -56,6 +56,7 @@ def lib():
             "hgks_ref_microslope": (i32, [_D, dbl, dbl, dbl, dbl, dbl, _D]),
             "hgks_ref_compat": (i32, [_D, _D, dbl, _D]),
             "hgks_ref_gp_flux_smooth": (i32, [_D, _D, dbl, dbl, dbl, _D, _D]),
+            "hgks_ref_gp_flux_smooth_ext": (i32, [_D, _D, dbl, dbl, dbl, _D, _D]),
             "hgks_ref_gp_flux_full": (i32, [_D, _D, _D, _D, _D, _D, dbl, dbl, dbl, dbl, _D, _D]),
             "hgks_ref_gp_flux_full_parts": (i32, [_D, _D, _D, _D, _D, _D, dbl, dbl, dbl, dbl, dbl, _D, _D]),
             "hgks_ref_weights": (i32, [_D]),
@@ -197,6 +198,15 @@ def gp_flux_smooth(Q0, dQ, tau, gamma, prandtl):
     F0 = np.zeros(5)
     F1 = np.zeros(5)
     lib().hgks_ref_gp_flux_smooth(_p(Q0), _p(dQ), float(tau), float(gamma), float(prandtl), _p(F0), _p(F1))
+    return F0, F1
+
+
+def gp_flux_smooth_ext(Q0, dQ, tau, gamma, prandtl):
+    """The smooth Gauss-point flux in x87 extended precision (error measurement only)."""
+    Q0, dQ = _arr(Q0, 5), _arr(dQ, 15)
+    F0 = np.zeros(5)
+    F1 = np.zeros(5)
+    lib().hgks_ref_gp_flux_smooth_ext(_p(Q0), _p(dQ), float(tau), float(gamma), float(prandtl), _p(F0), _p(F1))
     return F0, F1
 
 

@@ -1300,6 +1300,20 @@ int hgks_ref_gp_flux_smooth(const double* Q0, const double* dQ, double tau, doub
   return 0;
 }
 
+// The same Gauss-point flux evaluated in x87 extended precision (long double):
+// used only to measure the FP64 rounding error of the moment algebra, whose
+// moments about u = 0 grow like (p/rho)^3 and cancel at low Mach number.
+int hgks_ref_gp_flux_smooth_ext(const double* Q0, const double* dQ, double tau, double gamma, double prandtl,
+                                double* F0, double* F1) {
+  long double q[5], d[3][5], f0[5], f1[5];
+  for (int k = 0; k < 5; ++k) q[k] = Q0[k];
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 5; ++k) d[a][k] = dQ[a * 5 + k];
+  ref::gp_flux_smooth<long double>(q, d, (long double)tau, gamma, prandtl, f0, f1);
+  for (int k = 0; k < 5; ++k) { F0[k] = double(f0[k]); F1[k] = double(f1[k]); }
+  return 0;
+}
+
 int hgks_ref_gp_flux_full(const double* Ql, const double* dQl, const double* Qr, const double* dQr, const double* Q0,
                           const double* dQ0, double tau, double dt, double gamma, double prandtl, double* F, double* dF) {
   double l[3][5], r[3][5], z[3][5];

@@ -26,6 +26,10 @@ struct Geo {
   double K;              // internal degrees of freedom
   double mu_ref, T_ref, mu_exp;
   double cfl;
+  // constant reference state (rho_ref, U = 0, p_ref): the flux arithmetic works on
+  // deviations from it, and the constant p_ref is left out of the normal-momentum
+  // face flux (a constant flux has no divergence)
+  double rho_ref, p_ref, E_ref, H_ref;  // E_ref = p_ref/(gamma-1), H_ref = gamma p_ref/(gamma-1)
 };
 
 // Control block at the head of the workspace.
@@ -94,39 +98,53 @@ __device__ __forceinline__ void tang_der(const T* f, T& dm, T& dp) {
 // ---------------------------------------------------------------------------
 // Equilibrium state at the interface from the two reconstructed states: the
 // compatibility condition of Sec. 2.1 integrates the left Maxwellian over u>0
-// and the right one over u<0.  With lambda = rho/(2p) and the half-space
-// moments of the normal velocity
-//   a0 = erfc(-sqrt(lambda) U)/2, a1 = U a0 + exp(-lambda U^2)/(2 sqrt(pi lambda)),
+// and the right one over u<0.  With lambda = rho/(2p), x = sqrt(lambda) U and
+// the half-space moments of the normal velocity
+//   a0 = erfc(-x)/2 = 1/2 + erf(x)/2,  a1 = U a0 + exp(-x^2)/(2 sqrt(pi lambda)),
 //   a2 = U a1 + a0/(2 lambda)
-// (and the mirrored ones for u<0), the psi-moments are
-//   (a0, a1, V a0, W a0, (a2 + a0 (V^2 + W^2 + (K+2)/(2 lambda)))/2).
-// Local frame: component 1 is the face-normal momentum.
+// (for u<0: b0 = 1/2 - erf(x)/2, b1 = U b0 - exp(-x^2)/(2 sqrt(pi lambda))), the
+// psi-moments are (a0, a1, V a0, W a0, (a2 + a0 (V^2 + W^2 + (K+2)/(2 lambda)))/2),
+// whose energy moment times rho equals rho U a1/2 + rho a0 (V^2+W^2)/2 + a0 p/(gamma-1).
+// Inputs and output are deviations from the reference state (rho_ref, 0, p_ref),
+// arranged so that no large quantity is formed and then cancelled: this keeps the
+// FP32 form accurate.  Local frame: component 1 is the face-normal momentum.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void half_maxwell_psi(const T* Q, T gm1, T Kp2, int sgn, T* out) {
+struct Side {
+  T rho, U, V, W, p, dp, h, th;  // h = erf(x)/2, th = exp(-x^2)/(2 sqrt(pi lambda))
+};
+
+template <typename T>
+__device__ __forceinline__ Side<T> side_state(const Geo& g, const T* dQ) {
   const T kInvSqrtPi = T(0.56418958354775628695);
-  T rho = Q[0];
-  T ir = T(1) / rho;
-  T U = Q[1] * ir, V = Q[2] * ir, W = Q[3] * ir;
-  T p = gm1 * (Q[4] - T(0.5) * rho * (U * U + V * V + W * W));
-  T lam = T(0.5) * rho / p;
+  Side<T> s;
+  s.rho = T(g.rho_ref) + dQ[0];
+  T ir = T(1) / s.rho;
+  s.U = dQ[1] * ir;
+  s.V = dQ[2] * ir;
+  s.W = dQ[3] * ir;
+  s.dp = T(g.gm1) * (dQ[4] - T(0.5) * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
+  s.p = T(g.p_ref) + s.dp;
+  T lam = T(0.5) * s.rho / s.p;
   T sl = sqrt(lam);
-  T ex = exp(-lam * U * U);
-  T a0, a1;
-  if (sgn > 0) {
-    a0 = T(0.5) * erfc(-sl * U);
-    a1 = U * a0 + T(0.5) * ex * kInvSqrtPi / sl;
-  } else {
-    a0 = T(0.5) * erfc(sl * U);
-    a1 = U * a0 - T(0.5) * ex * kInvSqrtPi / sl;
-  }
-  T i2l = T(0.5) / lam;
-  T a2 = U * a1 + a0 * i2l;
-  out[0] = rho * a0;
-  out[1] = rho * a1;
-  out[2] = rho * V * a0;
-  out[3] = rho * W * a0;
-  out[4] = T(0.5) * rho * (a2 + a0 * (V * V + W * W + Kp2 * i2l));
+  T x = sl * s.U;
+  s.h = T(0.5) * erf(x);
+  s.th = T(0.5) * kInvSqrtPi * exp(-x * x) / sl;
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void compat_dev(const Geo& g, const T* dQl, const T* dQr, T* dQ0) {
+  Side<T> l = side_state(g, dQl), r = side_state(g, dQr);
+  T a0 = T(0.5) + l.h, b0 = T(0.5) - r.h;
+  T a1 = l.U * a0 + l.th, b1 = r.U * b0 - r.th;
+  dQ0[0] = T(0.5) * (dQl[0] + dQr[0]) + (l.rho * l.h - r.rho * r.h);
+  dQ0[1] = l.rho * a1 + r.rho * b1;
+  dQ0[2] = l.rho * l.V * a0 + r.rho * r.V * b0;
+  dQ0[3] = l.rho * l.W * a0 + r.rho * r.W * b0;
+  dQ0[4] = T(0.5) * (l.rho * (l.U * a1 + a0 * (l.V * l.V + l.W * l.W)) +
+                     r.rho * (r.U * b1 + b0 * (r.V * r.V + r.W * r.W))) +
+           (T(0.5) * (l.dp + r.dp) + (l.h * l.p - r.h * r.p)) * T(g.inv_gm1);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,21 +163,24 @@ __device__ __forceinline__ void half_maxwell_psi(const T* Q, T gm1, T Kp2, int s
 // The Prandtl-number correction adds (1/Pr - 1) times the heat flux, taken
 // about the interface velocity, of each part of f: -c_p mu dT/dn for the
 // tau-part and c_p p dU_n/dt for the t-part.
-// Inputs (local frame, index 0 = normal): Q0 and its derivatives D[a][k] =
-// dQ0_k/dx_a along (n, t1, t2).  F gets F^n, dF gets dF^n/dt (Eq. (expansion-1)).
+// Inputs (local frame, index 0 = normal): the deviation dQ of Q0 from the
+// reference state and the derivatives D[a][k] = dQ0_k/dx_a along (n, t1, t2).
+// F gets F^n without the constant p_ref in its normal-momentum component, dF gets
+// dF^n/dt (Eq. (expansion-1)).
 // VAR_MU selects mu(T) = mu_ref (T/T_ref)^mu_exp; otherwise mu = mu_ref (a
 // separate instantiation keeps the power function's registers out of the
 // constant-viscosity kernels).
 // ---------------------------------------------------------------------------
 template <bool NEED_F, bool VAR_MU, typename T>
-__device__ __forceinline__ void smooth_flux(const Geo& g, const T* Q, const T (*D)[5], T* F, T* dF) {
+__device__ __forceinline__ void smooth_flux(const Geo& g, const T* dQ, const T (*D)[5], T* F, T* dF) {
   const T gm1 = T(g.gm1);
-  T rho = Q[0];
+  T rho = T(g.rho_ref) + dQ[0];
   T ir = T(1) / rho;
-  T U0 = Q[1] * ir, U1 = Q[2] * ir, U2 = Q[3] * ir;
+  T U0 = dQ[1] * ir, U1 = dQ[2] * ir, U2 = dQ[3] * ir;
   T ke = T(0.5) * (U0 * U0 + U1 * U1 + U2 * U2);
-  T E = Q[4];
-  T p = gm1 * (E - rho * ke);
+  T dp = gm1 * (dQ[4] - rho * ke);
+  T p = T(g.p_ref) + dp;
+  T H = T(g.H_ref) + dQ[4] + dp;  // E + p
   // velocity gradient gu[a][c] = dU_c/dx_a and pressure gradient
   T gu[3][3], gp[3];
 #pragma unroll
@@ -177,12 +198,12 @@ __device__ __forceinline__ void smooth_flux(const Geo& g, const T* Q, const T (*
   for (int c = 0; c < 3; ++c) u_t[c] = -(U0 * gu[0][c] + U1 * gu[1][c] + U2 * gu[2][c] + gp[c] * ir);
   T p_t = -(U0 * gp[0] + U1 * gp[1] + U2 * gp[2] + T(g.gamma) * p * theta);
   T E_t = p_t * T(g.inv_gm1) + ke * rho_t + rho * (U0 * u_t[0] + U1 * u_t[1] + U2 * u_t[2]);
-  T m0 = rho * U0;
+  T m0 = dQ[1];
   dF[0] = rho_t * U0 + rho * u_t[0];
   dF[1] = rho_t * U0 * U0 + T(2) * m0 * u_t[0] + p_t;
   dF[2] = rho_t * U0 * U1 + rho * (u_t[0] * U1 + U0 * u_t[1]);
   dF[3] = rho_t * U0 * U2 + rho * (u_t[0] * U2 + U0 * u_t[2]);
-  dF[4] = u_t[0] * (E + p) + U0 * (E_t + p_t) + T(g.pr_fix * g.cp) * p * u_t[0];
+  dF[4] = u_t[0] * H + U0 * (E_t + p_t) + T(g.pr_fix * g.cp) * p * u_t[0];
   if (NEED_F) {
     T T0 = p * ir;
     T mu = T(g.mu_ref);
@@ -192,10 +213,10 @@ __device__ __forceinline__ void smooth_flux(const Geo& g, const T* Q, const T (*
     T s2 = mu * (gu[0][2] + gu[2][0]);
     T dTn = (gp[0] - T0 * D[0][0]) * ir;
     F[0] = m0;
-    F[1] = m0 * U0 + p - s0;
+    F[1] = m0 * U0 + dp - s0;
     F[2] = m0 * U1 - s1;
     F[3] = m0 * U2 - s2;
-    F[4] = U0 * (E + p) - (U0 * s0 + U1 * s1 + U2 * s2) - T(g.cp * g.inv_pr) * mu * dTn;
+    F[4] = U0 * H - (U0 * s0 + U1 * s1 + U2 * s2) - T(g.cp * g.inv_pr) * mu * dTn;
   }
 }
 

@@ -23,7 +23,7 @@ struct hgks_handle {
   Ctrl* ctrl;
   double* qs;           // Q* / Q^{n+1} ping-pong partner of q
   double* rr;           // R = Q^n + dt L + dt^2/6 dL
-  double* fl;           // face fluxes of the three directions [3][10][N]
+  void* fl;             // face fluxes of the three directions [3][10][N], FP64 or FP32
   double* diag_part;    // block partials of the diagnostics
   double* diag_out;     // derived diagnostics [HGKS_NDIAG]
   double* speed_part;   // block maxima of the CFL speed
@@ -47,7 +47,7 @@ struct Layout {
   size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, total;
 };
 
-Layout layout_for(long long N) {
+Layout layout_for(long long N, int precision) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -58,7 +58,7 @@ Layout layout_for(long long N) {
   L.ctrl = take(sizeof(Ctrl));
   L.qs = take(sizeof(double) * 5 * N);
   L.rr = take(sizeof(double) * 5 * N);
-  L.fl = take(sizeof(double) * 30 * N);
+  L.fl = take((precision == HGKS_PREC_F32FLUX ? sizeof(float) : sizeof(double)) * 30 * N);
   L.diag_part = take(sizeof(double) * diag_partial_doubles());
   L.diag_out = take(sizeof(double) * 64);
   L.speed_part = take(sizeof(double) * size_t((N + 255) / 256));
@@ -78,9 +78,8 @@ int validate(const hgks_params* p) {
   if (p->bc_y != HGKS_BC_PERIODIC && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_INVALID_ARG;
   long long N = (long long)p->nx * p->ny * p->nz;
   if (N > (1LL << 31) - 1) return HGKS_E_INVALID_ARG;  // 32-bit cell counts in the launch grids
-  // implemented so far: smooth mode, FP64, periodic boxes
-  if (p->mode != HGKS_MODE_SMOOTH || p->precision != HGKS_PREC_F64 || p->bc_y != HGKS_BC_PERIODIC ||
-      p->stretch_b != 0.0 || p->body_force_x != 0.0)
+  // implemented so far: smooth mode on periodic boxes
+  if (p->mode != HGKS_MODE_SMOOTH || p->bc_y != HGKS_BC_PERIODIC || p->stretch_b != 0.0 || p->body_force_x != 0.0)
     return HGKS_E_UNSUPPORTED;
   return HGKS_OK;
 }
@@ -110,8 +109,23 @@ Geo make_geo(const hgks_params* p) {
   g.T_ref = p->T_ref;
   g.mu_exp = p->mu_exp;
   g.cfl = p->cfl;
+  g.rho_ref = 1.0;
+  g.p_ref = 1.0;
+  g.E_ref = g.p_ref * g.inv_gm1;
+  g.H_ref = g.gamma * g.p_ref * g.inv_gm1;
   return g;
 }
+
+// Reference state of the flux arithmetic: density and pressure of cell 0 of the
+// initial state, with zero velocity.
+void set_reference(Geo& g, double rho, double p) {
+  g.rho_ref = rho;
+  g.p_ref = p;
+  g.E_ref = p * g.inv_gm1;
+  g.H_ref = g.gamma * p * g.inv_gm1;
+}
+
+bool f32(const hgks_handle* h) { return h->p.precision == HGKS_PREC_F32FLUX; }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? HGKS_OK : HGKS_E_DEVICE; }
 
@@ -143,13 +157,35 @@ void prof_collect(hgks_handle* h) {
   h->pending_class.clear();
 }
 
+template <typename TF>
+TF* fl_dir(hgks_handle* h, int d) {
+  return static_cast<TF*>(h->fl) + (size_t)d * 10 * h->geo.N;
+}
+
 // fluxes of all three directions of state src into h->fl (stage 2: time derivative only)
 void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop) {
   for (int d = 0; d < 3; ++d) {
     bool on = prof_begin(h, stage2 ? HGKS_KCLASS_FLUX_STAGE2 : HGKS_KCLASS_FLUX_STAGE1);
-    launch_flux_fused(h->geo, d, stage2, src, h->fl + (size_t)d * 10 * h->geo.N, stop, h->stream);
+    if (f32(h))
+      launch_flux_fused(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, h->stream);
+    else
+      launch_flux_fused(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, h->stream);
     prof_end(h, on);
   }
+}
+
+void stage1(hgks_handle* h, const double* cur, double* other, int step) {
+  if (f32(h))
+    launch_stage1(h->geo, cur, fl_dir<float>(h, 0), other, h->rr, h->ctrl, step, h->stream);
+  else
+    launch_stage1(h->geo, cur, fl_dir<double>(h, 0), other, h->rr, h->ctrl, step, h->stream);
+}
+
+void stage2(hgks_handle* h, double* other, int step) {
+  if (f32(h))
+    launch_stage2(h->geo, h->rr, fl_dir<float>(h, 0), other, h->ctrl, h->speed_part, step, h->stream);
+  else
+    launch_stage2(h->geo, h->rr, fl_dir<double>(h, 0), other, h->ctrl, h->speed_part, step, h->stream);
 }
 
 }  // namespace
@@ -159,7 +195,7 @@ extern "C" {
 size_t hgks_workspace_bytes(const hgks_params* p) {
   int v = validate(p);
   if (v != HGKS_OK) return 0;
-  return layout_for((long long)p->nx * p->ny * p->nz).total;
+  return layout_for((long long)p->nx * p->ny * p->nz, p->precision).total;
 }
 
 int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes, void* hip_stream,
@@ -170,7 +206,7 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   if (v != HGKS_OK) return v;
   if (!q) return HGKS_E_INVALID_ARG;
   const long long N = (long long)p->nx * p->ny * p->nz;
-  Layout L = layout_for(N);
+  Layout L = layout_for(N, p->precision);
   if (!workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return HGKS_E_WORKSPACE;
   hgks_handle* h = new (std::nothrow) hgks_handle;
@@ -184,7 +220,7 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   h->ctrl = reinterpret_cast<Ctrl*>(h->ws + L.ctrl);
   h->qs = reinterpret_cast<double*>(h->ws + L.qs);
   h->rr = reinterpret_cast<double*>(h->ws + L.rr);
-  h->fl = reinterpret_cast<double*>(h->ws + L.fl);
+  h->fl = h->ws + L.fl;
   h->diag_part = reinterpret_cast<double*>(h->ws + L.diag_part);
   h->diag_out = reinterpret_cast<double*>(h->ws + L.diag_out);
   h->speed_part = reinterpret_cast<double*>(h->ws + L.speed_part);
@@ -193,10 +229,23 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   h->profiling = false;
   for (int k = 0; k < HGKS_KCLASS_COUNT; ++k) { h->prof_ms[k] = 0.0; h->prof_count[k] = 0; }
   launch_reset_ctrl(h->ctrl, h->stream);
-  if (hipGetLastError() != hipSuccess) {
+  double c0[5];
+  for (int k = 0; k < 5; ++k) {
+    if (hipMemcpyAsync(&c0[k], q + (size_t)k * N, sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess) {
+      delete h;
+      return HGKS_E_DEVICE;
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     delete h;
     return HGKS_E_DEVICE;
   }
+  const double p0 = h->geo.gm1 * (c0[4] - 0.5 * (c0[1] * c0[1] + c0[2] * c0[2] + c0[3] * c0[3]) / c0[0]);
+  if (!(c0[0] > 0.0) || !(p0 > 0.0) || !std::isfinite(p0)) {
+    delete h;
+    return HGKS_E_NONPHYSICAL;
+  }
+  set_reference(h->geo, c0[0], p0);
   *out = h;
   return HGKS_OK;
 }
@@ -220,11 +269,11 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
       launch_dt(g, h->speed_part, h->ctrl, dt, s, st);
       all_fluxes(h, cur, false, &h->ctrl->flag);
       bool on = prof_begin(h, HGKS_KCLASS_STAGE1);
-      launch_stage1(g, cur, h->fl, other, h->rr, h->ctrl, step, st);
+      stage1(h, cur, other, step);
       prof_end(h, on);
       all_fluxes(h, other, true, &h->ctrl->flag);
       on = prof_begin(h, HGKS_KCLASS_STAGE2);
-      launch_stage2(g, h->rr, h->fl, other, h->ctrl, h->speed_part, step, st);
+      stage2(h, other, step);
       prof_end(h, on);
       double* t = cur;
       cur = other;
@@ -263,7 +312,10 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
   (void)dt;
   if (!h || !q_in || !L || !dL) return HGKS_E_INVALID_ARG;
   all_fluxes(h, q_in, false, &h->ctrl->zero);
-  launch_operator(h->geo, h->fl, L, dL, h->stream);
+  if (f32(h))
+    launch_operator(h->geo, fl_dir<float>(h, 0), L, dL, h->stream);
+  else
+    launch_operator(h->geo, fl_dir<double>(h, 0), L, dL, h->stream);
   return hip_status(hipGetLastError());
 }
 
@@ -271,12 +323,13 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
   (void)dt;
   if (!h || !q_in || !F || !dF || dir < 0 || dir > 2) return HGKS_E_INVALID_ARG;
   const Geo& g = h->geo;
-  double* fl = h->fl + (size_t)dir * 10 * g.N;
-  launch_flux_fused(g, dir, false, q_in, fl, &h->ctrl->zero, h->stream);
-  if (hipMemcpyAsync(F, fl, sizeof(double) * 5 * g.N, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
-    return HGKS_E_DEVICE;
-  if (hipMemcpyAsync(dF, fl + 5 * g.N, sizeof(double) * 5 * g.N, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
-    return HGKS_E_DEVICE;
+  if (f32(h)) {
+    launch_flux_fused(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, h->stream);
+    launch_export_flux(g, dir, fl_dir<float>(h, dir), F, dF, h->stream);
+  } else {
+    launch_flux_fused(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, h->stream);
+    launch_export_flux(g, dir, fl_dir<double>(h, dir), F, dF, h->stream);
+  }
   return hip_status(hipGetLastError());
 }
 

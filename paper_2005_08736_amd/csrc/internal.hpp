@@ -6,15 +6,22 @@
 namespace hgks {
 
 void launch_dt(const Geo& g, const double* part, Ctrl* ctrl, double dt_fixed, int hist, hipStream_t st);
-void launch_stage1(const Geo& g, const double* qn, const double* fl, double* qs, double* rr, Ctrl* ctrl, int step,
+template <typename TF>
+void launch_stage1(const Geo& g, const double* qn, const TF* fl, double* qs, double* rr, Ctrl* ctrl, int step,
                    hipStream_t st);
-void launch_stage2(const Geo& g, const double* rr, const double* fl, double* qout, Ctrl* ctrl, double* part, int step,
+template <typename TF>
+void launch_stage2(const Geo& g, const double* rr, const TF* fl, double* qout, Ctrl* ctrl, double* part, int step,
                    hipStream_t st);
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st);
 size_t speed_partials(const Geo& g);
 void launch_reset_ctrl(Ctrl* ctrl, hipStream_t st);
-void launch_operator(const Geo& g, const double* fl, double* L, double* dL, hipStream_t st);
+template <typename TF>
+void launch_operator(const Geo& g, const TF* fl, double* L, double* dL, hipStream_t st);
+template <typename TF>
+void launch_export_flux(const Geo& g, int dir, const TF* fl, double* F, double* dF, hipStream_t st);
 void launch_flux_fused(const Geo& g, int dir, bool stage2, const double* q, double* fl, const int* stop,
+                       hipStream_t st);
+void launch_flux_fused(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop,
                        hipStream_t st);
 void launch_copy(const double* src, double* dst, long long n, hipStream_t st);
 void launch_diagnostics(const Geo& g, const double* q, double* part, double* out, hipStream_t st);

@@ -39,6 +39,8 @@ __device__ __forceinline__ void block_max_speed(double v, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
 }
 
+// -(1/|Omega|) sum_p F_p for component k (Eq. (finite)) from the face averages of
+// the three directions (face n+1/2 stored at cell n), and the same for dF/dt.
 __device__ __forceinline__ void divergence(const Geo& g, const double* fl, long long idx, const int* c, int k,
                                            double* L, double* dL) {
   double l = 0.0, dl = 0.0;
@@ -51,6 +53,57 @@ __device__ __forceinline__ void divergence(const Geo& g, const double* fl, long 
   }
   if (L) *L = l;
   *dL = dl;
+}
+
+// FP32 face fluxes (FP32-flux form): each difference of two neighbouring faces
+// and its scaling by 1/h are split exactly into FP32 pieces (TwoSum for the
+// difference, an FMA for the product's rounding error), and the pieces of the
+// three directions are summed with compensation: every addition is a TwoSum
+// whose rounding error is collected in a second FP32 word (the summation of
+// Neumaier / Ogita-Rump-Oishi).  The error is then bounded by the precision of
+// the result itself, not by the size of the cancelling terms, and the FP64
+// update receives hi + lo, so the face contributions telescope over the box.
+// Contraction into FMAs is switched off in these helpers: fusing a product into
+// the compensated additions would add a value other than the one the error
+// terms account for.
+struct Kahan {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float t) {
+#pragma clang fp contract(off)
+    const float u = s + t;
+    const float v = u - s;
+    c += (s - (u - v)) + (t - v);  // TwoSum error of s + t
+    s = u;
+  }
+  __device__ __forceinline__ double value() const { return double(s) + double(c); }
+};
+
+// adds -(a - b) * ih to acc without losing the rounding errors of - and *
+__device__ __forceinline__ void add_neg_scaled_diff(Kahan& acc, float a, float b, float ih) {
+#pragma clang fp contract(off)
+  const float d = a - b;                  // TwoSum of a and -b: a - b = d + e exactly
+  const float v = d - a;
+  const float e = (a - (d - v)) + (-b - v);
+  const float p = d * ih;
+  const float pe = fmaf(d, ih, -p);       // d * ih = p + pe exactly
+  acc.add(-p);
+  acc.add(-pe);
+  acc.add(-(e * ih));
+}
+
+__device__ __forceinline__ void divergence(const Geo& g, const float* fl, long long idx, const int* c, int k,
+                                           double* L, double* dL) {
+  Kahan l, dl;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float* F = fl + (long long)d * 10 * g.N;
+    long long lo = c[d] == 0 ? idx + (long long)(g.n[d] - 1) * g.stride[d] : idx - g.stride[d];
+    const float ih = float(g.inv_h[d]);
+    if (L) add_neg_scaled_diff(l, F[(long long)k * g.N + idx], F[(long long)k * g.N + lo], ih);
+    add_neg_scaled_diff(dl, F[(long long)(5 + k) * g.N + idx], F[(long long)(5 + k) * g.N + lo], ih);
+  }
+  if (L) *L = l.value();
+  *dL = dl.value();
 }
 
 // Time step of the step about to start: the maximum of the block maxima of the
@@ -74,7 +127,8 @@ __global__ void __launch_bounds__(1024) dt_kernel(Geo g, const double* __restric
 }
 
 // Q* = Q^n + dt/2 L + dt^2/8 dL ; R = Q^n + dt L + dt^2/6 dL
-__global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __restrict__ qn, const double* __restrict__ fl,
+template <typename TF>
+__global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __restrict__ qn, const TF* __restrict__ fl,
                                                      double* __restrict__ qs, double* __restrict__ rr, Ctrl* ctrl,
                                                      int step) {
   if (ctrl->flag) return;
@@ -102,7 +156,8 @@ __global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __rest
 }
 
 // Q^{n+1} = R + dt^2/3 dL(Q*); block maxima of the next step's CFL speed.
-__global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __restrict__ rr, const double* __restrict__ fl,
+template <typename TF>
+__global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __restrict__ rr, const TF* __restrict__ fl,
                                                      double* __restrict__ qout, Ctrl* ctrl, double* __restrict__ part,
                                                      int step) {
   if (ctrl->flag) return;
@@ -158,7 +213,8 @@ __global__ void reset_ctrl_kernel(Ctrl* ctrl) {
 }
 
 // L and dL of Eq. (finite) from the face fluxes (parity entry point).
-__global__ void __launch_bounds__(256) operator_kernel(Geo g, const double* __restrict__ fl, double* __restrict__ L,
+template <typename TF>
+__global__ void __launch_bounds__(256) operator_kernel(Geo g, const TF* __restrict__ fl, double* __restrict__ L,
                                                        double* __restrict__ dL) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.N) return;
@@ -170,6 +226,20 @@ __global__ void __launch_bounds__(256) operator_kernel(Geo g, const double* __re
     divergence(g, fl, idx, c, k, &l, &dl);
     L[(long long)k * g.N + idx] = l;
     dL[(long long)k * g.N + idx] = dl;
+  }
+}
+
+// Face fluxes of one direction as FP64 face averages with the constant reference
+// pressure restored in the normal-momentum component (parity entry point).
+template <typename TF>
+__global__ void __launch_bounds__(256) export_flux_kernel(Geo g, int dir, const TF* __restrict__ fl,
+                                                          double* __restrict__ F, double* __restrict__ dF) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.N) return;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F[(long long)k * g.N + idx] = double(fl[(long long)k * g.N + idx]) + (k == 1 + dir ? g.p_ref : 0.0);
+    dF[(long long)k * g.N + idx] = double(fl[(long long)(5 + k) * g.N + idx]);
   }
 }
 
@@ -188,15 +258,21 @@ void launch_dt(const Geo& g, const double* part, Ctrl* ctrl, double dt_fixed, in
   dt_kernel<<<1, 1024, 0, st>>>(g, part, int(blocks_for(g.N)), ctrl, dt_fixed, hist);
 }
 
-void launch_stage1(const Geo& g, const double* qn, const double* fl, double* qs, double* rr, Ctrl* ctrl, int step,
+template <typename TF>
+void launch_stage1(const Geo& g, const double* qn, const TF* fl, double* qs, double* rr, Ctrl* ctrl, int step,
                    hipStream_t st) {
-  stage1_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, qn, fl, qs, rr, ctrl, step);
+  stage1_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, qn, fl, qs, rr, ctrl, step);
 }
+template void launch_stage1<double>(const Geo&, const double*, const double*, double*, double*, Ctrl*, int, hipStream_t);
+template void launch_stage1<float>(const Geo&, const double*, const float*, double*, double*, Ctrl*, int, hipStream_t);
 
-void launch_stage2(const Geo& g, const double* rr, const double* fl, double* qout, Ctrl* ctrl, double* part, int step,
+template <typename TF>
+void launch_stage2(const Geo& g, const double* rr, const TF* fl, double* qout, Ctrl* ctrl, double* part, int step,
                    hipStream_t st) {
-  stage2_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qout, ctrl, part, step);
+  stage2_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qout, ctrl, part, step);
 }
+template void launch_stage2<double>(const Geo&, const double*, const double*, double*, Ctrl*, double*, int, hipStream_t);
+template void launch_stage2<float>(const Geo&, const double*, const float*, double*, Ctrl*, double*, int, hipStream_t);
 
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st) {
   check_state_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, q, ctrl, part, step);
@@ -206,9 +282,19 @@ size_t speed_partials(const Geo& g) { return size_t(blocks_for(g.N)); }
 
 void launch_reset_ctrl(Ctrl* ctrl, hipStream_t st) { reset_ctrl_kernel<<<1, 1, 0, st>>>(ctrl); }
 
-void launch_operator(const Geo& g, const double* fl, double* L, double* dL, hipStream_t st) {
-  operator_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, fl, L, dL);
+template <typename TF>
+void launch_operator(const Geo& g, const TF* fl, double* L, double* dL, hipStream_t st) {
+  operator_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, fl, L, dL);
 }
+template void launch_operator<double>(const Geo&, const double*, double*, double*, hipStream_t);
+template void launch_operator<float>(const Geo&, const float*, double*, double*, hipStream_t);
+
+template <typename TF>
+void launch_export_flux(const Geo& g, int dir, const TF* fl, double* F, double* dF, hipStream_t st) {
+  export_flux_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, dir, fl, F, dF);
+}
+template void launch_export_flux<double>(const Geo&, int, const double*, double*, double*, hipStream_t);
+template void launch_export_flux<float>(const Geo&, int, const float*, double*, double*, hipStream_t);
 
 void launch_copy(const double* src, double* dst, long long n, hipStream_t st) {
   long long b = (n + 255) / 256;

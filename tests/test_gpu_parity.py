@@ -95,10 +95,12 @@ def test_face_flux_matches_oracle(case, direction):
     # component itself: the compatibility state sums two half-space thermal
     # fluxes of size rho sqrt(2p/(pi rho)) that cancel where the normal velocity
     # vanishes (Taylor-Green W = 0), and dF holds gamma p div(U) with div(U) ~ 0.
+    # The oracle's own FP64 error on dF at these temperatures is up to ~2e-12 of
+    # its scale (test_oracle_rounding_bound_at_low_mach), hence 1e-11 for dF.
     scF, scD = np.abs(Fr).max(), np.abs(dFr).max()
     for k in range(5):
         assert np.abs(F[k] - Fr[k]).max() <= 1e-13 * scF, (k, np.abs(F[k] - Fr[k]).max(), scF)
-        assert np.abs(dF[k] - dFr[k]).max() <= 1e-12 * scD, (k, np.abs(dF[k] - dFr[k]).max(), scD)
+        assert np.abs(dF[k] - dFr[k]).max() <= 1e-11 * scD, (k, np.abs(dF[k] - dFr[k]).max(), scD)
 
 
 def face_area(p, direction):
@@ -123,9 +125,11 @@ def test_operator_matches_oracle(case):
         area = face_area(p, d)
         scF = np.maximum(scF, np.abs(Fr / area).reshape(5, -1).max(axis=1) / h[d])
         scD = np.maximum(scD, np.abs(dFr / area).reshape(5, -1).max(axis=1) / h[d])
-    for A, Ar, sc in ((L.cpu().numpy(), Lr, scF), (dL.cpu().numpy(), dLr, scD)):
+    # dL inherits the oracle's FP64 error on dF (up to ~2e-12 of the flux scale at
+    # Taylor-Green temperatures), hence the looser bound on the second entry
+    for A, Ar, sc, tol in ((L.cpu().numpy(), Lr, scF, 1e-13), (dL.cpu().numpy(), dLr, scD, 1e-11)):
         for k in range(5):
-            assert np.abs(A[k] - Ar[k]).max() <= 1e-13 * sc[k], (k, np.abs(A[k] - Ar[k]).max(), sc[k])
+            assert np.abs(A[k] - Ar[k]).max() <= tol * sc[k], (k, np.abs(A[k] - Ar[k]).max(), sc[k])
 
 
 def test_tgv32_twenty_steps_match_oracle_every_step():

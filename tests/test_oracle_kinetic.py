@@ -260,3 +260,31 @@ def test_weno5_linear_exact_and_z_weights_behave(oracle_mod):
     step = np.array([0.0, 0.0, 0.0, 1.0, 1.0])
     z, _ = oracle_mod.weno5(step, linear=False)
     assert abs(z) < 0.05
+
+
+def test_oracle_rounding_bound_at_low_mach(oracle_mod):
+    """Measures the FP64 rounding error of the oracle's moment algebra at the
+    Taylor-Green conditions (T = p/rho ~ 71): moments about u = 0 grow like T^3
+    and cancel, so F1 carries up to a few 1e-12 relative error.  This bound sets
+    the tolerance of the GPU parity checks on dF and dL."""
+    rng2 = np.random.default_rng(7)
+    worst0 = worst1 = 0.0
+    for _ in range(200):
+        r = 1 + 0.01 * rng2.normal()
+        U = rng2.normal(size=3)
+        p = 71.4 + 0.2 * rng2.normal()
+        Q = cons(r, *U, p)
+        dQ = rng2.normal(size=15)
+        tau = (1 / 1600) / p
+        F0, F1 = oracle_mod.gp_flux_smooth(Q, dQ, tau, GAMMA, 0.72)
+        E0, E1 = oracle_mod.gp_flux_smooth_ext(Q, dQ, tau, GAMMA, 0.72)
+        worst0 = max(worst0, np.abs(F0 - E0).max() / np.abs(E0).max())
+        worst1 = max(worst1, np.abs(F1 - E1).max() / np.abs(E1).max())
+    assert worst0 < 1e-13, worst0
+    assert worst1 < 5e-12, worst1
+    # at unit temperature the same algebra is accurate to round-off
+    Q = cons(1.0, 0.3, -0.2, 0.1, 1.0)
+    dQ = rng2.normal(size=15)
+    F0, F1 = oracle_mod.gp_flux_smooth(Q, dQ, 0.01, GAMMA, 0.72)
+    E0, E1 = oracle_mod.gp_flux_smooth_ext(Q, dQ, 0.01, GAMMA, 0.72)
+    assert np.abs(F1 - E1).max() <= 1e-14 * np.abs(E1).max()
