@@ -109,6 +109,19 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
  * [5][nz][ny][nx] each.  A parity aid; no synchronization. */
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF);
 
+/* Adjoint of one two-stage step (Eq. (two-stage)) with the time step dt frozen
+ * (dt > 0): given the state q_n the step starts from and the cotangent lam_np1 of
+ * the state after the step, writes lam_n = (dQ^{n+1}/dQ^n)^T lam_np1.  All three
+ * are device [5][nz][ny][nx] and lam_n must not overlap q_n or lam_np1.  The
+ * first stage is recomputed from q_n; the reverse sweep runs the hand-written
+ * adjoint of the face-flux kernels (Gauss-point flux, tangential and normal
+ * reconstruction, compatibility state) and of the stage formulas.  Device
+ * atomics accumulate the cell cotangents, so repeated calls agree to rounding,
+ * not bitwise.  Smooth mode with constant viscosity and FP64 arithmetic;
+ * HGKS_E_UNSUPPORTED otherwise.  Enqueued on the handle's stream, no
+ * synchronization; the bound state is not touched. */
+int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
+
 /* Global FP64 diagnostics of the bound state (Sec. 3.1, 3.4): out (host) receives
  * HGKS_NDIAG doubles in this order:
  *   0..4 totals sum Q_k |Omega_i|; 5 E_k; 6 enstrophy zeta; 7 eps1; 8 eps2;

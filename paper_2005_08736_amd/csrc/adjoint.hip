@@ -1,0 +1,219 @@
+// Adjoint (vector-Jacobian product) of the HGKS operator and of the two-stage
+// step, hand-written for gfx950.
+//
+// Operator: L_i = -sum_d (F_d(i+1/2) - F_d(i-1/2)) / h_d and the same for dL with
+// dF (Eq. (finite)).  For cotangents mu_L, mu_dL on the cells, the cotangent of
+// a face flux is (mu(i+1) - mu(i)) / h_d.  The kernel of direction DIR works on
+// the same tiles as the forward kernel:
+//   1. recompute the face field of the tile and halo into LDS (exactly the
+//      forward arithmetic, flux_tile.hpp);
+//   2. per face: recompute the Gauss-point data, run the reverse of the
+//      gas-kinetic flux at each Gauss point (adjoint_common.hpp) and transpose the
+//      tangential reconstruction, adding the face-field cotangents of the 5 x 5
+//      neighbourhood into an LDS tile (LDS atomics);
+//   3. per face-field entry: reverse the compatibility state and the normal
+//      reconstruction and add the cell cotangents into lambda (global atomics).
+// Mixing the two cotangent sources mu = cA * A + cB * B inside the kernel lets one
+// launch per direction serve both stages of the step adjoint.
+#include "adjoint_common.hpp"
+#include "flux_tile.hpp"
+#include "internal.hpp"
+
+namespace hgks {
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void global_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int DIR, bool NEED_F>
+__global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __restrict__ q,
+                                                       const double* __restrict__ A, const double* __restrict__ B,
+                                                       double cLA, double cLB, double cDA, double cDB,
+                                                       double* __restrict__ lam, int ntx, int nty, int ntz, int nper) {
+  using T = double;
+  using TG = TileGeom<DIR>;
+  __shared__ T ff[10 * TG::NFF];
+  __shared__ T ffb[10 * TG::NFF];
+  const int tile = tile_of_block(nper);
+  if (tile >= ntx * nty * ntz) return;
+  const int x0 = (tile % ntx) * TG::BX;
+  const int y0 = ((tile / ntx) % nty) * TG::BY;
+  const int z0 = (tile / (ntx * nty)) * TG::BZ;
+  const int tid = threadIdx.x;
+
+  face_field_tile<T, DIR>(g, q, ff, x0, y0, z0);
+  for (int e = tid; e < 10 * TG::NFF; e += 256) ffb[e] = T(0);
+  __syncthreads();
+
+  // ---- phase 2: per face
+  {
+    const int fx = tid % TG::BX, fy = (tid / TG::BX) % TG::BY, fz = tid / (TG::BX * TG::BY);
+    const int gx = x0 + fx, gy = y0 + fy, gz = z0 + fz;
+    if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2]) {
+      constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
+      constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
+      const int centre = (fx + TG::HX) + (fy + TG::HY) * TG::FX + (fz + TG::HZ) * TG::FX * TG::FY;
+      const int corner = centre - 2 * s1 - 2 * s2;
+      const T i1 = T(g.inv_h[A1]), i2 = T(g.inv_h[A2]);
+      // cotangents of the face average (local frame): (mu(i+1) - mu(i)) / h, then 1/4 per Gauss point
+      const long long idx = (long long)gx + (long long)gy * g.stride[1] + (long long)gz * g.stride[2];
+      int c[3] = {gx, gy, gz};
+      const long long up = c[DIR] == g.n[DIR] - 1 ? idx - (long long)(g.n[DIR] - 1) * g.stride[DIR]
+                                                  : idx + g.stride[DIR];
+      T Fb[5], dFb[5];
+      const T w = T(0.25 * g.inv_h[DIR]);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const long long o = (long long)gcomp_local<DIR>(k) * g.N;
+        T a = A[o + up] - A[o + idx];
+        T b = B ? B[o + up] - B[o + idx] : T(0);
+        Fb[k] = NEED_F ? w * (T(cLA) * a + T(cLB) * b) : T(0);
+        dFb[k] = w * (T(cDA) * a + T(cDB) * b);
+      }
+#pragma unroll 1
+      for (int m = 0; m < 2; ++m) {
+        T Qg[2][5], Dg[2][3][5];
+        gp_data<T, DIR>(ff, corner, m, i1, i2, Qg, Dg);
+        T Qgb[2][5], Dgb[2][3][5];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            Qgb[l][k] = T(0);
+            Dgb[l][0][k] = Dgb[l][1][k] = Dgb[l][2][k] = T(0);
+          }
+          smooth_flux_vjp<NEED_F, false>(g, Qg[l], Dg[l], Fb, dFb, Qgb[l], Dgb[l]);
+        }
+        // transpose of the tangential reconstruction for this m
+        T wvm[5], wdm[5], wv0[5], wd0[5], wv1[5], wd1[5];
+        tang_weights(m, wvm, wdm);
+        tang_weights(0, wv0, wd0);
+        tang_weights(1, wv1, wd1);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          T* f0b = ffb + k * TG::NFF + corner;
+          T* fnb = ffb + (5 + k) * TG::NFF + corner;
+#pragma unroll
+          for (int r = 0; r < 5; ++r) {
+            // cotangents of the row values at (m, row r): value, t1-derivative, normal slope
+            T rv = wv0[r] * Qgb[0][k] + wv1[r] * Qgb[1][k] + (wd0[r] * Dgb[0][2][k] + wd1[r] * Dgb[1][2][k]) * i2;
+            T rd = (wv0[r] * Dgb[0][1][k] + wv1[r] * Dgb[1][1][k]) * i1;
+            T rn = wv0[r] * Dgb[0][0][k] + wv1[r] * Dgb[1][0][k];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+              lds_add(f0b + a * s1 + r * s2, wvm[a] * rv + wdm[a] * rd);
+              lds_add(fnb + a * s1 + r * s2, wvm[a] * rn);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 3: per face-field entry, reverse compatibility + normal reconstruction
+  const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
+  for (int e = tid; e < TG::NFF; e += 256) {
+    T Q0b[5], Dnb[5];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      Q0b[k] = ffb[k * TG::NFF + e];
+      Dnb[k] = ffb[(5 + k) * TG::NFF + e];
+      any = any || Q0b[k] != T(0) || Dnb[k] != T(0);
+    }
+    if (!any) continue;
+    T v[5][6];
+    long long off[6];
+    normal_stencil<T, DIR>(g, q, e, x0, y0, z0, v, off);
+    T Ql[5], Qr[5], Dn[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
+    T Qlb[5] = {0, 0, 0, 0, 0}, Qrb[5] = {0, 0, 0, 0, 0};
+    compat_dev_vjp(g, Ql, Qr, Q0b, Qlb, Qrb);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      T vb[6];
+      const T l = Qlb[k] * T(1.0 / 60.0), r = Qrb[k] * T(1.0 / 60.0), d = Dnb[k] * ih12;
+      vb[0] = T(2) * l;
+      vb[1] = T(-13) * l - T(3) * r + d;
+      vb[2] = T(47) * l + T(27) * r - T(15) * d;
+      vb[3] = T(27) * l + T(47) * r + T(15) * d;
+      vb[4] = T(-3) * l - T(13) * r - d;
+      vb[5] = T(2) * r;
+      double* out = lam + (long long)gcomp_local<DIR>(k) * g.N;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) global_add(out + off[j], vb[j]);
+    }
+  }
+}
+
+template <int DIR>
+void tile_grid(const Geo& g, int& ntx, int& nty, int& ntz, int& nper);
+
+template <int DIR, bool NEED_F>
+static void launch_vjp_dir(const Geo& g, const double* q, const double* A, const double* B, double cLA, double cLB,
+                           double cDA, double cDB, double* lam, hipStream_t st) {
+  int ntx, nty, ntz, nper;
+  tile_grid<DIR>(g, ntx, nty, ntz, nper);
+  flux_vjp_kernel<DIR, NEED_F><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, A, B, cLA, cLB, cDA, cDB, lam,
+                                                                                ntx, nty, ntz, nper);
+}
+
+// lam += (dL/dQ)^T mu_L + (ddL/dQ)^T mu_dL at state q, with mu_L = cLA A + cLB B and
+// mu_dL = cDA A + cDB B (B may be null).
+void launch_operator_vjp(const Geo& g, const double* q, const double* A, const double* B, double cLA, double cLB,
+                         double cDA, double cDB, double* lam, hipStream_t st) {
+  const bool need_f = cLA != 0.0 || cLB != 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (need_f) {
+      if (d == 0) launch_vjp_dir<0, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+      else if (d == 1) launch_vjp_dir<1, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+      else launch_vjp_dir<2, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    } else {
+      if (d == 0) launch_vjp_dir<0, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+      else if (d == 1) launch_vjp_dir<1, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+      else launch_vjp_dir<2, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    }
+  }
+}
+
+// out = a * X + b * Y (elementwise over n doubles)
+__global__ void __launch_bounds__(256) axpby_kernel(double a, const double* __restrict__ X, double b,
+                                                    const double* __restrict__ Y, double* __restrict__ out, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = a * X[i] + b * Y[i];
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(double* __restrict__ out, double v, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = v;
+}
+
+__global__ void set_dt_kernel(Ctrl* ctrl, double dt) {
+  ctrl->dt = dt;
+  ctrl->flag = 0;
+  ctrl->zero = 0;
+}
+
+static unsigned grid_for(long long n) {
+  long long b = (n + 255) / 256;
+  return unsigned(b > 65536 ? 65536 : b);
+}
+
+void launch_axpby(double a, const double* X, double b, const double* Y, double* out, long long n, hipStream_t st) {
+  axpby_kernel<<<grid_for(n), 256, 0, st>>>(a, X, b, Y, out, n);
+}
+
+void launch_fill(double* out, double v, long long n, hipStream_t st) { fill_kernel<<<grid_for(n), 256, 0, st>>>(out, v, n); }
+
+void launch_set_dt(Ctrl* ctrl, double dt, hipStream_t st) { set_dt_kernel<<<1, 1, 0, st>>>(ctrl, dt); }
+
+}  // namespace hgks

@@ -44,7 +44,7 @@ struct Ctrl {
   double dt_hist[kDtHist];         // time step of each step of the current call
 };
 
-__device__ __forceinline__ int wrapi(int i, int n) {
+__host__ __device__ __forceinline__ int wrapi(int i, int n) {
   i = i < 0 ? i + n : i;
   return i >= n ? i - n : i;
 }
@@ -81,14 +81,14 @@ constexpr double kDa2 = -1.0 / 12.0;
 // Tangential reconstruction of one field along a line of five face values f[0..4]
 // (f[2] the middle face): values and derivatives at the -/+ Gauss points.
 template <typename T>
-__device__ __forceinline__ void tang_val(const T* f, T& vm, T& vp) {
+__host__ __device__ __forceinline__ void tang_val(const T* f, T& vm, T& vp) {
   T e = T(kVe0) * f[2] + T(kVe1) * (f[1] + f[3]) + T(kVe2) * (f[0] + f[4]);
   T o = T(kVo1) * (f[3] - f[1]) + T(kVo2) * (f[4] - f[0]);
   vm = e - o;
   vp = e + o;
 }
 template <typename T>
-__device__ __forceinline__ void tang_der(const T* f, T& dm, T& dp) {
+__host__ __device__ __forceinline__ void tang_der(const T* f, T& dm, T& dp) {
   T s = T(kDs0) * f[2] + T(kDs1) * (f[1] + f[3]) + T(kDs2) * (f[0] + f[4]);
   T a = T(kDa1) * (f[3] - f[1]) + T(kDa2) * (f[4] - f[0]);
   dm = a - s;
@@ -115,7 +115,7 @@ struct Side {
 };
 
 template <typename T>
-__device__ __forceinline__ Side<T> side_state(const Geo& g, const T* dQ) {
+__host__ __device__ __forceinline__ Side<T> side_state(const Geo& g, const T* dQ) {
   const T kInvSqrtPi = T(0.56418958354775628695);
   Side<T> s;
   s.rho = T(g.rho_ref) + dQ[0];
@@ -134,7 +134,7 @@ __device__ __forceinline__ Side<T> side_state(const Geo& g, const T* dQ) {
 }
 
 template <typename T>
-__device__ __forceinline__ void compat_dev(const Geo& g, const T* dQl, const T* dQr, T* dQ0) {
+__host__ __device__ __forceinline__ void compat_dev(const Geo& g, const T* dQl, const T* dQr, T* dQ0) {
   Side<T> l = side_state(g, dQl), r = side_state(g, dQr);
   T a0 = T(0.5) + l.h, b0 = T(0.5) - r.h;
   T a1 = l.U * a0 + l.th, b1 = r.U * b0 - r.th;
@@ -172,7 +172,7 @@ __device__ __forceinline__ void compat_dev(const Geo& g, const T* dQl, const T* 
 // constant-viscosity kernels).
 // ---------------------------------------------------------------------------
 template <bool NEED_F, bool VAR_MU, typename T>
-__device__ __forceinline__ void smooth_flux(const Geo& g, const T* dQ, const T (*D)[5], T* F, T* dF) {
+__host__ __device__ __forceinline__ void smooth_flux(const Geo& g, const T* dQ, const T (*D)[5], T* F, T* dF) {
   const T gm1 = T(g.gm1);
   T rho = T(g.rho_ref) + dQ[0];
   T ir = T(1) / rho;

@@ -1,0 +1,169 @@
+// Tile geometry and the two reconstruction phases shared by the fused face-flux
+// kernel (flux_fused.hip) and its adjoint (adjoint.hip), so that the adjoint
+// recomputes exactly the forward arithmetic.
+//
+// A workgroup of 256 threads owns a tile of 256 faces of direction DIR plus a
+// halo of two faces along both tangential axes.  x-faces use a 4 x 8 x 8 tile
+// (halo in y and z), y- and z-faces 32 x 8 along x and the other tangential axis,
+// so that x, the contiguous axis, stays fastest in every load.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace hgks {
+
+template <int DIR> struct FluxTile;
+template <> struct FluxTile<0> { static constexpr int B[3] = {4, 8, 8}; };
+template <> struct FluxTile<1> { static constexpr int B[3] = {32, 1, 8}; };
+template <> struct FluxTile<2> { static constexpr int B[3] = {32, 8, 1}; };
+
+template <int DIR>
+struct TileGeom {
+  static constexpr int BX = FluxTile<DIR>::B[0], BY = FluxTile<DIR>::B[1], BZ = FluxTile<DIR>::B[2];
+  static constexpr int HX = DIR == 0 ? 0 : 2, HY = DIR == 1 ? 0 : 2, HZ = DIR == 2 ? 0 : 2;
+  static constexpr int FX = BX + 2 * HX, FY = BY + 2 * HY, FZ = BZ + 2 * HZ;
+  static constexpr int NFF = FX * FY * FZ;
+  static constexpr int S[3] = {1, FX, FX * FY};  // LDS strides of the face-field tile
+  static_assert(BX * BY * BZ == 256, "one face per thread");
+};
+
+__device__ __forceinline__ int wrapmod(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// global component of local-frame component `local` for face direction DIR:
+// (rho, m_n, m_t1, m_t2, E) with (n, t1, t2) = (x, y, z), (y, z, x), (z, x, y)
+template <int DIR>
+__host__ __device__ __forceinline__ int gcomp_local(int local) {
+  return (local == 0 || local == 4) ? local : 1 + (DIR + local - 1) % 3;
+}
+
+// XCD-aware tile order: block b runs on XCD b % 8 and takes tile (b % 8) * nper + b / 8
+__device__ __forceinline__ int tile_of_block(int nper) { return int(blockIdx.x % 8u) * nper + int(blockIdx.x / 8u); }
+
+// Cell averages along the normal of face-field entry e (six cells n-2 .. n+3,
+// periodic), as deviations from the reference state, in the local frame; the
+// global cell offsets of the six cells are returned in off.
+template <typename T, int DIR>
+__device__ __forceinline__ void normal_stencil(const Geo& g, const double* __restrict__ q, int e, int x0, int y0,
+                                               int z0, T (*v)[6], long long* off) {
+  using TG = TileGeom<DIR>;
+  const int ex = e % TG::FX, ey = (e / TG::FX) % TG::FY, ez = e / (TG::FX * TG::FY);
+  int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), wrapmod(y0 + ey - TG::HY, g.n[1]), wrapmod(z0 + ez - TG::HZ, g.n[2])};
+  const int nn = c[DIR], Nn = g.n[DIR];
+  const long long sn = g.stride[DIR];
+  const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
+                         (long long)nn * sn;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) off[m] = base + (long long)wrapi(nn - 2 + m, Nn) * sn;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double* f = q + (long long)gcomp_local<DIR>(k) * g.N;
+    const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v[k][m] = T(f[off[m]] - ref);
+  }
+}
+
+// Normal reconstruction at the face between cells 2 and 3 of the six:
+// fifth-order left/right values (WENO5 with its optimal linear weights) and the
+// derivative of the cubic through the four middle cells.
+template <typename T>
+__host__ __device__ __forceinline__ void normal_recon(const T* v, T ih12, T& ql, T& qr, T& dn) {
+  ql = (T(2) * v[0] - T(13) * v[1] + T(47) * v[2] + T(27) * v[3] - T(3) * v[4]) * T(1.0 / 60.0);
+  qr = (T(-3) * v[1] + T(27) * v[2] + T(47) * v[3] - T(13) * v[4] + T(2) * v[5]) * T(1.0 / 60.0);
+  dn = (v[1] - T(15) * v[2] + T(15) * v[3] - v[4]) * ih12;
+}
+
+// Phase 1: face field (Q0 deviation and dQ0/dn, local frame) of the tile and its
+// tangential halo into ff[10][NFF].  The caller synchronizes.
+template <typename T, int DIR>
+__device__ __forceinline__ void face_field_tile(const Geo& g, const double* __restrict__ q, T* ff, int x0, int y0,
+                                                int z0) {
+  using TG = TileGeom<DIR>;
+  const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
+  for (int e = threadIdx.x; e < TG::NFF; e += 256) {
+    T v[5][6];
+    long long off[6];
+    normal_stencil<T, DIR>(g, q, e, x0, y0, z0, v, off);
+    T Ql[5], Qr[5], Dn[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
+    T Q0[5];
+    compat_dev(g, Ql, Qr, Q0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ff[k * TG::NFF + e] = Q0[k];
+      ff[(5 + k) * TG::NFF + e] = Dn[k];
+    }
+  }
+}
+
+// Phase 2 data: tangential fourth-order reconstruction, for the t1 Gauss point m
+// and both t2 Gauss points l, of Q0 (value, d/dt1, d/dt2) and of dQ0/dn (value)
+// from the 5 x 5 face neighbourhood whose corner sits at LDS index `corner`.
+// Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).
+template <typename T, int DIR>
+__device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2, T (*Qg)[5], T (*Dg)[3][5]) {
+  using TG = TileGeom<DIR>;
+  constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
+  constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    // keep the scheduler from hoisting the next component's LDS reads: it would
+    // otherwise hold all 250 values at once and drop the occupancy to one wave
+    asm volatile("" ::: "memory");
+    const T* f0 = ff + k * TG::NFF + corner;
+    const T* fn = ff + (5 + k) * TG::NFF + corner;
+    T rv[5], rd[5], rn[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      T line[5], lined[5];
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        line[a] = f0[a * s1 + r * s2];
+        lined[a] = fn[a * s1 + r * s2];
+      }
+      T vm, vp, dm, dp, nm, np;
+      tang_val(line, vm, vp);
+      tang_der(line, dm, dp);
+      tang_val(lined, nm, np);
+      rv[r] = m ? vp : vm;
+      rd[r] = m ? dp : dm;
+      rn[r] = m ? np : nm;
+    }
+    T vm, vp, d2m, d2p, d1m, d1p, nm, np;
+    tang_val(rv, vm, vp);
+    tang_der(rv, d2m, d2p);
+    tang_val(rd, d1m, d1p);
+    tang_val(rn, nm, np);
+    Qg[0][k] = vm;
+    Qg[1][k] = vp;
+    Dg[0][0][k] = nm;
+    Dg[1][0][k] = np;
+    Dg[0][1][k] = d1m * i1;
+    Dg[1][1][k] = d1p * i1;
+    Dg[0][2][k] = d2m * i2;
+    Dg[1][2][k] = d2p * i2;
+  }
+}
+
+// Explicit tangential weights at Gauss point m (0: -, 1: +) for value and
+// derivative, cell order j-2 .. j+2 (the even/odd forms of tang_val/tang_der).
+template <typename T>
+__host__ __device__ __forceinline__ void tang_weights(int m, T* wv, T* wd) {
+  const T s = m ? T(1) : T(-1);
+  wv[0] = T(kVe2) - s * T(kVo2);
+  wv[1] = T(kVe1) - s * T(kVo1);
+  wv[2] = T(kVe0);
+  wv[3] = T(kVe1) + s * T(kVo1);
+  wv[4] = T(kVe2) + s * T(kVo2);
+  wd[0] = s * T(kDs2) - T(kDa2);
+  wd[1] = s * T(kDs1) - T(kDa1);
+  wd[2] = s * T(kDs0);
+  wd[3] = s * T(kDs1) + T(kDa1);
+  wd[4] = s * T(kDs2) + T(kDa2);
+}
+
+}  // namespace hgks

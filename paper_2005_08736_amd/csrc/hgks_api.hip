@@ -27,6 +27,7 @@ struct hgks_handle {
   double* diag_part;    // block partials of the diagnostics
   double* diag_out;     // derived diagnostics [HGKS_NDIAG]
   double* speed_part;   // block maxima of the CFL speed
+  double* lam_star;     // adjoint of Q* (step adjoint)
   long long steps_done; // steps advanced over the handle's lifetime
   int failed_step;
   // optional per-kernel timing
@@ -44,7 +45,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, total;
+  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, lam_star, total;
 };
 
 Layout layout_for(long long N, int precision) {
@@ -62,6 +63,7 @@ Layout layout_for(long long N, int precision) {
   L.diag_part = take(sizeof(double) * diag_partial_doubles());
   L.diag_out = take(sizeof(double) * 64);
   L.speed_part = take(sizeof(double) * size_t((N + 255) / 256));
+  L.lam_star = take(sizeof(double) * 5 * N);
   L.total = off;
   return L;
 }
@@ -224,6 +226,7 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   h->diag_part = reinterpret_cast<double*>(h->ws + L.diag_part);
   h->diag_out = reinterpret_cast<double*>(h->ws + L.diag_out);
   h->speed_part = reinterpret_cast<double*>(h->ws + L.speed_part);
+  h->lam_star = reinterpret_cast<double*>(h->ws + L.lam_star);
   h->steps_done = 0;
   h->failed_step = -1;
   h->profiling = false;
@@ -330,6 +333,27 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
     launch_flux_fused(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, h->stream);
     launch_export_flux(g, dir, fl_dir<double>(h, dir), F, dF, h->stream);
   }
+  return hip_status(hipGetLastError());
+}
+
+int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n) {
+  if (!h || !q_n || !lam_np1 || !lam_n || !(dt > 0.0)) return HGKS_E_INVALID_ARG;
+  if (lam_n == lam_np1 || lam_n == q_n) return HGKS_E_INVALID_ARG;
+  if (h->p.precision != HGKS_PREC_F64 || h->p.mu_exp != 0.0) return HGKS_E_UNSUPPORTED;
+  const Geo& g = h->geo;
+  hipStream_t st = h->stream;
+  const long long n5 = 5 * g.N;
+  // forward stage 1 with the frozen time step: Q* into the workspace
+  launch_set_dt(h->ctrl, dt, st);
+  all_fluxes(h, q_n, false, &h->ctrl->zero);
+  stage1(h, q_n, h->qs, -1);
+  // lambda* = (ddL/dQ)^T(Q*) (dt^2/3 lambda)
+  launch_fill(h->lam_star, 0.0, n5, st);
+  launch_operator_vjp(g, h->qs, lam_np1, nullptr, 0.0, 0.0, dt * dt / 3.0, 0.0, h->lam_star, st);
+  // lambda_n = lambda + lambda* + (dL/dQ)^T(Q^n) (dt lambda + dt/2 lambda*)
+  //                              + (ddL/dQ)^T(Q^n) (dt^2/6 lambda + dt^2/8 lambda*)
+  launch_axpby(1.0, lam_np1, 1.0, h->lam_star, lam_n, n5, st);
+  launch_operator_vjp(g, q_n, lam_np1, h->lam_star, dt, 0.5 * dt, dt * dt / 6.0, dt * dt / 8.0, lam_n, st);
   return hip_status(hipGetLastError());
 }
 

@@ -36,7 +36,7 @@ DIAG_NAMES = [
 EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
-    "hgks_profile_enable", "hgks_profile_read",
+    "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp",
 ]
 KCLASS_NAMES = ["face_field", "flux_stage1", "flux_stage2", "stage1", "stage2"]
 
@@ -95,6 +95,8 @@ def load():
     L.hgks_profile_enable.argtypes = [vp, ctypes.c_int]
     L.hgks_profile_read.restype = ctypes.c_int
     L.hgks_profile_read.argtypes = [vp, D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    L.hgks_step_vjp.restype = ctypes.c_int
+    L.hgks_step_vjp.argtypes = [vp, vp, dbl, vp, vp]
     L.hgks_strerror.restype = ctypes.c_char_p
     L.hgks_strerror.argtypes = [ctypes.c_int]
     _lib = L
@@ -175,6 +177,14 @@ class Solver:
                                      ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(dF.data_ptr())),
                "hgks_face_flux")
         return F, dF
+
+    def step_vjp(self, q_n: torch.Tensor, dt: float, lam_np1: torch.Tensor) -> torch.Tensor:
+        """(dQ^{n+1}/dQ^n)^T lam_np1 for one step of frozen dt starting at q_n."""
+        lam_n = torch.empty_like(self.q)
+        _check(load().hgks_step_vjp(self._h, ctypes.c_void_p(q_n.data_ptr()), float(dt),
+                                    ctypes.c_void_p(lam_np1.data_ptr()), ctypes.c_void_p(lam_n.data_ptr())),
+               "hgks_step_vjp")
+        return lam_n
 
     def diagnostics(self) -> dict:
         out = (ctypes.c_double * HGKS_NDIAG)()

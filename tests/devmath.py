@@ -1,0 +1,67 @@
+"""Builds and loads tests/cpp/devmath.hip: the library's scalar device math
+compiled for the host, for CPU checks of the forward and adjoint formulas."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cpp", "devmath.hip")
+LIB = os.path.join(HERE, "cpp", "libdevmath.so")
+HDRS = [os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", n) for n in ("device_common.hpp", "adjoint_common.hpp")]
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        newest = max(os.path.getmtime(p) for p in [SRC] + HDRS)
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
+            subprocess.run(["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                            "-o", LIB + ".tmp", SRC], check=True)
+            os.replace(LIB + ".tmp", LIB)
+        _lib = ctypes.CDLL(LIB)
+    return _lib
+
+
+def _a(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    assert a.size == n
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def smooth_flux(Q, D, gamma, prandtl, mu, rho_ref, p_ref):
+    Q, D = _a(Q, 5), _a(D, 15)
+    F, dF = np.zeros(5), np.zeros(5)
+    lib().dm_smooth_flux(_p(Q), _p(D), ctypes.c_double(gamma), ctypes.c_double(prandtl), ctypes.c_double(mu),
+                         ctypes.c_double(rho_ref), ctypes.c_double(p_ref), _p(F), _p(dF))
+    return F, dF
+
+
+def smooth_flux_vjp(Q, D, gamma, prandtl, mu, rho_ref, p_ref, Fb, dFb):
+    Q, D, Fb, dFb = _a(Q, 5), _a(D, 15), _a(Fb, 5), _a(dFb, 5)
+    Qb, Db = np.zeros(5), np.zeros(15)
+    lib().dm_smooth_flux_vjp(_p(Q), _p(D), ctypes.c_double(gamma), ctypes.c_double(prandtl), ctypes.c_double(mu),
+                             ctypes.c_double(rho_ref), ctypes.c_double(p_ref), _p(Fb), _p(dFb), _p(Qb), _p(Db))
+    return Qb, Db
+
+
+def compat(Ql, Qr, gamma, rho_ref, p_ref):
+    Ql, Qr = _a(Ql, 5), _a(Qr, 5)
+    Q0 = np.zeros(5)
+    lib().dm_compat(_p(Ql), _p(Qr), ctypes.c_double(gamma), ctypes.c_double(rho_ref), ctypes.c_double(p_ref), _p(Q0))
+    return Q0
+
+
+def compat_vjp(Ql, Qr, gamma, rho_ref, p_ref, Q0b):
+    Ql, Qr, Q0b = _a(Ql, 5), _a(Qr, 5), _a(Q0b, 5)
+    Qlb, Qrb = np.zeros(5), np.zeros(5)
+    lib().dm_compat_vjp(_p(Ql), _p(Qr), ctypes.c_double(gamma), ctypes.c_double(rho_ref), ctypes.c_double(p_ref),
+                        _p(Q0b), _p(Qlb), _p(Qrb))
+    return Qlb, Qrb

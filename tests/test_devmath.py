@@ -1,0 +1,86 @@
+"""CPU checks of the library's scalar device math, built for the host from the
+same headers the kernels use: the Gauss-point flux and compatibility state
+against the oracle, and the hand-written vector-Jacobian products against
+central differences of the forward functions (no GPU needed)."""
+import numpy as np
+import pytest
+
+from tests import devmath
+
+GAMMA = 1.4
+rng = np.random.default_rng(11)
+
+
+def cons(r, U, p, g=GAMMA):
+    return np.array([r, r * U[0], r * U[1], r * U[2], p / (g - 1) + 0.5 * r * (U @ U)])
+
+
+def states(p_level):
+    r = 1 + 0.05 * rng.normal()
+    return cons(r, rng.normal(size=3), p_level * (1 + 0.01 * rng.normal()))
+
+
+@pytest.mark.parametrize("p_level", [1.0, 71.4])
+def test_device_flux_and_compat_match_oracle(oracle_mod, p_level):
+    rho_ref, p_ref = 1.0, p_level
+    for _ in range(20):
+        Q = states(p_level)
+        D = rng.normal(size=15)
+        mu = 1e-3
+        F, dF = devmath.smooth_flux(Q, D, GAMMA, 0.72, mu, rho_ref, p_ref)
+        F[1] += p_ref
+        r = Q[0]
+        p = (GAMMA - 1) * (Q[4] - 0.5 * (Q[1:4] @ Q[1:4]) / r)
+        F0, F1 = oracle_mod.gp_flux_smooth(Q, D, mu / p, GAMMA, 0.72)
+        assert np.abs(F - F0).max() <= 1e-13 * np.abs(F0).max()
+        # the oracle's F1 carries up to ~2e-12 relative rounding at p ~ 71
+        assert np.abs(dF - F1).max() <= 5e-12 * np.abs(F1).max()
+        Ql, Qr = states(p_level), states(p_level)
+        Q0 = devmath.compat(Ql, Qr, GAMMA, rho_ref, p_ref)
+        assert np.abs(Q0 - oracle_mod.compat(Ql, Qr, GAMMA)).max() <= 1e-13 * np.abs(Q0).max()
+
+
+def _fd_check(f, x, v, wb, h):
+    """<wb, J v> by central differences of f at x along v, Richardson-extrapolated
+    over steps h and h/2 (truncation error O(h^4))."""
+    def cd(hh):
+        return float(wb @ ((f(x + hh * v) - f(x - hh * v)) / (2 * hh)))
+    return (4 * cd(h / 2) - cd(h)) / 3
+
+
+@pytest.mark.parametrize("p_level", [1.0, 71.4])
+def test_smooth_flux_vjp_matches_central_differences(p_level):
+    rho_ref, p_ref = 1.0, p_level
+    for _ in range(10):
+        Q = states(p_level)
+        D = rng.normal(size=15)
+        Fb, dFb = rng.normal(size=5), rng.normal(size=5)
+
+        def f(x):
+            F, dF = devmath.smooth_flux(x[:5], x[5:], GAMMA, 0.72, 2e-3, rho_ref, p_ref)
+            return np.concatenate([F, dF])
+
+        x = np.concatenate([Q, D])
+        v = rng.normal(size=20)
+        Qb, Db = devmath.smooth_flux_vjp(Q, D, GAMMA, 0.72, 2e-3, rho_ref, p_ref, Fb, dFb)
+        lhs = float(np.concatenate([Qb, Db]) @ v)
+        rhs = _fd_check(f, x, v, np.concatenate([Fb, dFb]), 1e-6 * max(1.0, np.abs(x).max()))
+        assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+@pytest.mark.parametrize("p_level", [1.0, 71.4])
+def test_compat_vjp_matches_central_differences(p_level):
+    rho_ref, p_ref = 1.0, p_level
+    for _ in range(10):
+        Ql, Qr = states(p_level), states(p_level)
+        Q0b = rng.normal(size=5)
+
+        def f(x):
+            return devmath.compat(x[:5], x[5:], GAMMA, rho_ref, p_ref)
+
+        x = np.concatenate([Ql, Qr])
+        v = rng.normal(size=10)
+        Qlb, Qrb = devmath.compat_vjp(Ql, Qr, GAMMA, rho_ref, p_ref, Q0b)
+        lhs = float(np.concatenate([Qlb, Qrb]) @ v)
+        rhs = _fd_check(f, x, v, Q0b, 1e-6 * max(1.0, np.abs(x).max()))
+        assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(rhs)), (lhs, rhs)
