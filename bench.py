@@ -38,16 +38,18 @@ PEAK_HBM_GBS = 8000.0
 # operations (FMA = 2, SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / faces) by rocprofv3
 # on the unfused kernels, where every face was computed exactly once.
 FLUX_STAGE1_FLOPS_PER_FACE = 639 + 2320
-# HBM bytes per face of the stage-1 flux kernel from rocprofv3 FETCH_SIZE +
-# WRITE_SIZE, scaled by the copy-kernel calibration factor; valid only for the
-# kernel source with this digest.
-FLUX_STAGE1_HBM_BYTES_PER_FACE = None
-FLUX_COUNTERS_SOURCE_DIGEST = None
+# HBM bytes per face of the stage-1 flux kernel (mean of the three directions)
+# from two rocprofv3 --pmc passes, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the
+# factors make the same counters read the known 671 MB in / 671 MB out of the
+# library's copy kernel.  Valid only for the kernel sources with this digest
+# (profiles/flux_fused_tgv256_counters.md).
+FLUX_STAGE1_HBM_BYTES_PER_FACE = 174.3
+FLUX_COUNTERS_SOURCE_DIGEST = "3ea2dce5ef51b37f"
 
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for name in ("flux_fused.hip", "device_common.hpp"):
+    for name in ("flux_fused.hip", "flux_tile.hpp", "device_common.hpp"):
         with open(os.path.join(ROOT, "paper_2005_08736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -78,14 +80,52 @@ def cpu_baseline(n_cpu: int, steps: int):
     }
 
 
+def adjoint_timing(r, reps, torch):
+    """Time of one step adjoint (hgks_step_vjp, which recomputes the first stage
+    itself) at the current state of the FP64 run, and the cost of a reverse step
+    under checkpointing (the forward recompute of the step's input plus its
+    adjoint) relative to a forward step."""
+    s, q = r["solver"], r["q"]
+    dt = float(r["dts"][-1])
+    gen = torch.Generator(device=q.device).manual_seed(0)
+    lam = torch.randn(q.shape, dtype=q.dtype, device=q.device, generator=gen)
+    qn = q.clone()
+    s.step_vjp(qn, dt, lam)
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lam = s.step_vjp(qn, dt, lam)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    prof = s.profile_read()
+    s.profile(False)
+    if not bool(torch.isfinite(lam).all()):
+        raise RuntimeError("adjoint produced non-finite values")
+    ms_vjp, cnt_vjp = prof["operator_vjp"]
+    out = {
+        "ms_per_step_vjp": el * 1e3,
+        "ms_per_reverse_step_with_recompute": el * 1e3 + r["ms"],
+        "ratio_vs_forward_step": (el * 1e3 + r["ms"]) / r["ms"],
+        "vjp_only_ratio": el * 1e3 / r["ms"],
+        "operator_vjp_avg_launch_ms": ms_vjp / max(cnt_vjp, 1),
+        "workload": "same state and step as the forward run, FP64, dt frozen",
+    }
+    log(f"[bench] adjoint: {el * 1e3:.3f} ms per step VJP; reverse step with recompute / forward step = "
+        f"{out['ratio_vs_forward_step']:.2f}; operator_vjp {out['operator_vjp_avg_launch_ms']:.3f} ms per launch")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-n", type=int, default=96)
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--adjoint-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -132,6 +172,7 @@ def main():
         return dict(value=value, ms=el / args.steps * 1e3, prof=prof, dts=dts, solver=s, q=q)
 
     r64 = run(hgks.PREC_F64)
+    adj = adjoint_timing(r64, args.adjoint_reps, torch)
     r32 = run(hgks.PREC_F32FLUX)
     value = r64["value"]
     ms_per_step = r64["ms"]
@@ -186,6 +227,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "fp32_form": fp32,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -136,17 +136,19 @@ int hgks_diagnostics(hgks_handle* h, double* out);
 
 /* Per-kernel timing.  While enabled, hgks_step brackets every kernel launch with
  * HIP events recorded on the handle's stream and accumulates the elapsed times
- * per kernel class (see HGKS_KCLASS_*).  Enabling creates HIP events (host
- * runtime objects, no workspace use); disabling releases them.  hgks_profile_read
- * copies the accumulated milliseconds and launch counts of the first n classes
- * (ms and counts are host arrays of n entries) and resets the accumulators. */
+ * per kernel class (see HGKS_KCLASS_*); hgks_step_vjp does the same for its
+ * kernels.  Enabling creates HIP events (host runtime objects, no workspace use);
+ * disabling releases them.  hgks_profile_read synchronizes the stream, copies the
+ * accumulated milliseconds and launch counts of the first n classes (ms and counts
+ * are host arrays of n entries) and resets the accumulators. */
 enum {
-  HGKS_KCLASS_FACE_FIELD = 0, /* normal reconstruction + compatibility state */
-  HGKS_KCLASS_FLUX_STAGE1 = 1, /* tangential reconstruction + Gauss-point flux, stage 1 */
-  HGKS_KCLASS_FLUX_STAGE2 = 2, /* the same, stage 2 (time derivative only) */
-  HGKS_KCLASS_STAGE1 = 3,      /* divergence + Q*, R */
-  HGKS_KCLASS_STAGE2 = 4,      /* divergence + Q^{n+1} + CFL reduction */
-  HGKS_KCLASS_COUNT = 5
+  HGKS_KCLASS_DT = 0,           /* time step from the CFL block maxima */
+  HGKS_KCLASS_FLUX_STAGE1 = 1,  /* fused face flux of one direction, stage 1 (F and dF/dt) */
+  HGKS_KCLASS_FLUX_STAGE2 = 2,  /* the same, stage 2 (dF/dt only) */
+  HGKS_KCLASS_STAGE1 = 3,       /* divergence + Q*, R */
+  HGKS_KCLASS_STAGE2 = 4,       /* divergence + Q^{n+1} + CFL block maxima */
+  HGKS_KCLASS_OPERATOR_VJP = 5, /* adjoint of the face fluxes of one direction (hgks_step_vjp) */
+  HGKS_KCLASS_COUNT = 6
 };
 int hgks_profile_enable(hgks_handle* h, int enable);
 int hgks_profile_read(hgks_handle* h, double* ms, int64_t* counts, int n);

@@ -41,9 +41,8 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
   __shared__ T ffb[10 * TG::NFF];
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
-  const int x0 = (tile % ntx) * TG::BX;
-  const int y0 = ((tile / ntx) % nty) * TG::BY;
-  const int z0 = (tile / (ntx * nty)) * TG::BZ;
+  int x0, y0, z0;
+  tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
   const int tid = threadIdx.x;
 
   face_field_tile<T, DIR>(g, q, ff, x0, y0, z0);
@@ -165,21 +164,19 @@ static void launch_vjp_dir(const Geo& g, const double* q, const double* A, const
                                                                                 ntx, nty, ntz, nper);
 }
 
-// lam += (dL/dQ)^T mu_L + (ddL/dQ)^T mu_dL at state q, with mu_L = cLA A + cLB B and
-// mu_dL = cDA A + cDB B (B may be null).
-void launch_operator_vjp(const Geo& g, const double* q, const double* A, const double* B, double cLA, double cLB,
-                         double cDA, double cDB, double* lam, hipStream_t st) {
+// lam += (dL/dQ)^T mu_L + (ddL/dQ)^T mu_dL at state q for the faces of direction
+// dir, with mu_L = cLA A + cLB B and mu_dL = cDA A + cDB B (B may be null).
+void launch_operator_vjp(const Geo& g, int dir, const double* q, const double* A, const double* B, double cLA,
+                         double cLB, double cDA, double cDB, double* lam, hipStream_t st) {
   const bool need_f = cLA != 0.0 || cLB != 0.0;
-  for (int d = 0; d < 3; ++d) {
-    if (need_f) {
-      if (d == 0) launch_vjp_dir<0, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-      else if (d == 1) launch_vjp_dir<1, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-      else launch_vjp_dir<2, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    } else {
-      if (d == 0) launch_vjp_dir<0, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-      else if (d == 1) launch_vjp_dir<1, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-      else launch_vjp_dir<2, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    }
+  if (need_f) {
+    if (dir == 0) launch_vjp_dir<0, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else if (dir == 1) launch_vjp_dir<1, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else launch_vjp_dir<2, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+  } else {
+    if (dir == 0) launch_vjp_dir<0, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else if (dir == 1) launch_vjp_dir<1, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else launch_vjp_dir<2, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
   }
 }
 

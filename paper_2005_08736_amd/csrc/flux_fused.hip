@@ -26,9 +26,8 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   __shared__ T ff[10 * TG::NFF];
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
-  const int x0 = (tile % ntx) * TG::BX;
-  const int y0 = ((tile / ntx) % nty) * TG::BY;
-  const int z0 = (tile / (ntx * nty)) * TG::BZ;
+  int x0, y0, z0;
+  tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
 
   face_field_tile<T, DIR>(g, q, ff, x0, y0, z0);
   __syncthreads();

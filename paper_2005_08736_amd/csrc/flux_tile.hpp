@@ -42,6 +42,27 @@ __host__ __device__ __forceinline__ int gcomp_local(int local) {
 // XCD-aware tile order: block b runs on XCD b % 8 and takes tile (b % 8) * nper + b / 8
 __device__ __forceinline__ int tile_of_block(int nper) { return int(blockIdx.x % 8u) * nper + int(blockIdx.x / 8u); }
 
+// Origin (first face) of a tile.  Tiles are numbered with the normal axis of the
+// next tile sharing most of the stencil running fastest where that keeps the
+// stencil planes of the blocks resident at one time inside one XCD's L2: x-faces
+// and y-faces walk x first (a y-face tile is one face thick in y, so neighbouring
+// rows follow after ntx tiles), z-faces walk z first, because a z-face tile is one
+// plane and its six-plane stencil is shared with the next 5 tiles along z.
+template <int DIR>
+__device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
+  using TG = TileGeom<DIR>;
+  if (DIR == 2) {
+    z0 = (tile % ntz) * TG::BZ;
+    const int r = tile / ntz;
+    x0 = (r % ntx) * TG::BX;
+    y0 = (r / ntx) * TG::BY;
+  } else {
+    x0 = (tile % ntx) * TG::BX;
+    y0 = ((tile / ntx) % nty) * TG::BY;
+    z0 = (tile / (ntx * nty)) * TG::BZ;
+  }
+}
+
 // Cell averages along the normal of face-field entry e (six cells n-2 .. n+3,
 // periodic), as deviations from the reference state, in the local frame; the
 // global cell offsets of the six cells are returned in off.

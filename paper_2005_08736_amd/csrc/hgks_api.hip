@@ -176,6 +176,16 @@ void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop)
   }
 }
 
+// adjoint of the face fluxes of all three directions (one timed launch each)
+void operator_vjp(hgks_handle* h, const double* q, const double* A, const double* B, double cLA, double cLB,
+                  double cDA, double cDB, double* lam) {
+  for (int d = 0; d < 3; ++d) {
+    bool on = prof_begin(h, HGKS_KCLASS_OPERATOR_VJP);
+    launch_operator_vjp(h->geo, d, q, A, B, cLA, cLB, cDA, cDB, lam, h->stream);
+    prof_end(h, on);
+  }
+}
+
 void stage1(hgks_handle* h, const double* cur, double* other, int step) {
   if (f32(h))
     launch_stage1(h->geo, cur, fl_dir<float>(h, 0), other, h->rr, h->ctrl, step, h->stream);
@@ -269,9 +279,11 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
     double* other = h->qs;
     for (int s = 0; s < chunk; ++s) {
       const int step = int(s0 + done + s);
+      bool on = prof_begin(h, HGKS_KCLASS_DT);
       launch_dt(g, h->speed_part, h->ctrl, dt, s, st);
+      prof_end(h, on);
       all_fluxes(h, cur, false, &h->ctrl->flag);
-      bool on = prof_begin(h, HGKS_KCLASS_STAGE1);
+      on = prof_begin(h, HGKS_KCLASS_STAGE1);
       stage1(h, cur, other, step);
       prof_end(h, on);
       all_fluxes(h, other, true, &h->ctrl->flag);
@@ -349,11 +361,11 @@ int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* la
   stage1(h, q_n, h->qs, -1);
   // lambda* = (ddL/dQ)^T(Q*) (dt^2/3 lambda)
   launch_fill(h->lam_star, 0.0, n5, st);
-  launch_operator_vjp(g, h->qs, lam_np1, nullptr, 0.0, 0.0, dt * dt / 3.0, 0.0, h->lam_star, st);
+  operator_vjp(h, h->qs, lam_np1, nullptr, 0.0, 0.0, dt * dt / 3.0, 0.0, h->lam_star);
   // lambda_n = lambda + lambda* + (dL/dQ)^T(Q^n) (dt lambda + dt/2 lambda*)
   //                              + (ddL/dQ)^T(Q^n) (dt^2/6 lambda + dt^2/8 lambda*)
   launch_axpby(1.0, lam_np1, 1.0, h->lam_star, lam_n, n5, st);
-  launch_operator_vjp(g, q_n, lam_np1, h->lam_star, dt, 0.5 * dt, dt * dt / 6.0, dt * dt / 8.0, lam_n, st);
+  operator_vjp(h, q_n, lam_np1, h->lam_star, dt, 0.5 * dt, dt * dt / 6.0, dt * dt / 8.0, lam_n);
   return hip_status(hipGetLastError());
 }
 
@@ -380,6 +392,8 @@ int hgks_profile_enable(hgks_handle* h, int enable) {
 
 int hgks_profile_read(hgks_handle* h, double* ms, int64_t* counts, int n) {
   if (!h || !ms || !counts || n < 0 || n > HGKS_KCLASS_COUNT) return HGKS_E_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return HGKS_E_DEVICE;
+  prof_collect(h);
   for (int k = 0; k < n; ++k) {
     ms[k] = h->prof_ms[k];
     counts[k] = h->prof_count[k];

@@ -38,7 +38,7 @@ EXPORTED = [
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
     "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp",
 ]
-KCLASS_NAMES = ["face_field", "flux_stage1", "flux_stage2", "stage1", "stage2"]
+KCLASS_NAMES = ["dt", "flux_stage1", "flux_stage2", "stage1", "stage2", "operator_vjp"]
 
 
 class HgksParams(ctypes.Structure):
