@@ -48,8 +48,10 @@ enum {
 /* HGKS_MODE_SMOOTH: linear-weight WENO5 normal reconstruction, fourth-order
  *   tangential polynomials and the smooth second-order gas-kinetic flux
  *   (Remark 1 of Sec. 2.1; the Taylor-Green and channel cases).
- * HGKS_MODE_WENOZ: WENO-Z reconstruction and the full flux of Eq. (flux) with the
- *   artificial collision time of Sec. 3 (isotropic turbulence). */
+ * HGKS_MODE_WENOZ: WENO-Z reconstruction (weights of the Z type with exponent
+ *   weno_p in 1..4 and epsilon weno_eps > 0) in the normal direction and along
+ *   both tangential axes, and the full flux of Eq. (flux) integrated in time, with
+ *   the artificial collision time of Sec. 3 (c_art >= 0; isotropic turbulence). */
 enum { HGKS_MODE_SMOOTH = 0, HGKS_MODE_WENOZ = 1 };
 /* HGKS_PREC_F64: all arithmetic in FP64.
  * HGKS_PREC_F32FLUX: reconstruction and flux arithmetic in FP32 around FP64
@@ -99,14 +101,16 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken);
 
 /* Operator of Eq. (finite) and its time derivative at an arbitrary state:
  * L = L(q_in), dL = dL/dt(q_in), all device [5][nz][ny][nx].  dt enters only
- * mode-Z terms (artificial collision time, time integrals).  Enqueued on the
- * handle's stream, no synchronization. */
+ * mode-Z terms (artificial collision time, time integrals) and must be > 0 in
+ * that mode (HGKS_E_INVALID_ARG otherwise).  Enqueued on the handle's stream,
+ * no synchronization. */
 int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, double* dL);
 
 /* Face fluxes of direction dir (0 = x, 1 = y, 2 = z) of the state q_in: F^n and
  * dF^n/dt averaged over the face (divide-by-area form: 1/4 sum over the Gauss
  * points), global frame, face n+1/2 stored at the index of cell n.  Device
- * [5][nz][ny][nx] each.  A parity aid; no synchronization. */
+ * [5][nz][ny][nx] each.  dt as for hgks_operator.  A parity aid; no
+ * synchronization. */
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF);
 
 /* Adjoint of one two-stage step (Eq. (two-stage)) with the time step dt frozen
@@ -118,7 +122,7 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
  * reconstruction, compatibility state) and of the stage formulas.  Device
  * atomics accumulate the cell cotangents, so repeated calls agree to rounding,
  * not bitwise.  Smooth mode with constant viscosity and FP64 arithmetic;
- * HGKS_E_UNSUPPORTED otherwise.  Enqueued on the handle's stream, no
+ * HGKS_E_UNSUPPORTED otherwise (mode Z, mu(T), the FP32-flux form).  Enqueued on the handle's stream, no
  * synchronization; the bound state is not touched. */
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
 

@@ -30,6 +30,9 @@ struct Geo {
   // deviations from it, and the constant p_ref is left out of the normal-momentum
   // face flux (a constant flux has no divergence)
   double rho_ref, p_ref, E_ref, H_ref;  // E_ref = p_ref/(gamma-1), H_ref = gamma p_ref/(gamma-1)
+  // WENO-Z / full-flux mode: Z-weight epsilon and exponent, artificial collision-time coefficient
+  double weno_eps, c_art;
+  int weno_p;
 };
 
 // Control block at the head of the workspace.

@@ -1,0 +1,287 @@
+// Fused face-flux kernel of the WENO-Z / full-flux mode (mode Z), one face
+// direction per launch, LDS-tiled for gfx950.
+//
+// A workgroup of 256 threads owns 8 x 8 faces of direction DIR (one face thick
+// along the normal) and works in three phases:
+//   1. face field of the tile and a two-face halo in both tangential axes
+//      (12 x 12 entries) into LDS: for each conservative component, the WENO-Z
+//      values Q_l, Q_r and slopes dQ_l/dn, dQ_r/dn from the six cells along the
+//      normal, the equilibrium state Q0 by the compatibility condition and dQ0/dn
+//      (Sec. 2.1): 30 fields;
+//   2. WENO-Z edge values, along t1, of the middle face of every five-face t1
+//      line centred on a tile column (8 x 12 lines per field) into LDS;
+//   3. one thread per Gauss point (4 per face): the parabola through each line's
+//      average and edge values gives the line's value and t1-derivative at the
+//      t1 Gauss point; WENO-Z across the five lines in t2 and a second parabola
+//      give the field's value and both tangential derivatives at the Gauss point
+//      (60 values), from which the full gas distribution of Eq. (flux), integrated
+//      over dt and dt/2, gives F^n and dF^n/dt (Eq. (expansion-1)).  The four
+//      Gauss points of a face sit in adjacent lanes and are summed with shuffles.
+// Tiles are numbered with the normal axis fastest (neighbouring tiles along the
+// normal share five of their six stencil planes) and dealt to the XCDs in
+// contiguous ranges.
+#include "flux_tile.hpp"
+#include "internal.hpp"
+#include "zflux.hpp"
+
+namespace hgks {
+
+template <int DIR>
+struct ZTileGeom {
+  static constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;  // t1, t2 axes
+  static constexpr int B = 8;                                   // faces per tangential axis
+  static constexpr int P = B + 4;                               // with the halo
+  static constexpr int NFF = P * P;                             // face-field entries (t1 fastest)
+  static constexpr int NROW = B * P;                            // t1 lines (t1 in the tile, t2 with halo)
+  static constexpr int NF = 30;                                 // fields per entry
+};
+
+// field numbering in LDS
+constexpr int kZQ0 = 0, kZDn = 5, kZQl = 10, kZQr = 15, kZDl = 20, kZDr = 25;
+
+template <typename T, int DIR>
+__device__ __forceinline__ void zface_field(const Geo& g, const double* __restrict__ q, T* ff, int on, int o1, int o2) {
+  using TG = ZTileGeom<DIR>;
+  const T ih = T(g.inv_h[DIR]);
+  const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
+  const T eps = T(g.weno_eps);
+  for (int e = threadIdx.x; e < TG::NFF; e += 256) {
+    const int i1 = e % TG::P, i2 = e / TG::P;
+    int c[3];
+    c[DIR] = on;
+    c[TG::A1] = wrapmod(o1 + i1 - 2, g.n[TG::A1]);
+    c[TG::A2] = wrapmod(o2 + i2 - 2, g.n[TG::A2]);
+    const int Nn = g.n[DIR];
+    const long long sn = g.stride[DIR];
+    const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
+                           (long long)on * sn;
+    T Ql[5], Qr[5], Dl[5], Dr[5], Dn[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double* f = q + (long long)gcomp_local<DIR>(k) * g.N;
+      const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+      T v[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v[m] = T(f[base + (long long)wrapi(on - 2 + m, Nn) * sn] - ref);
+      T sl, sr;
+      weno_z_right(v, eps, g.weno_p, Ql[k], sl);
+      T rv[5] = {v[5], v[4], v[3], v[2], v[1]};
+      weno_z_right(rv, eps, g.weno_p, Qr[k], sr);
+      Dl[k] = sl * ih;
+      Dr[k] = -sr * ih;
+      Dn[k] = (v[1] - T(15) * v[2] + T(15) * v[3] - v[4]) * ih12;
+    }
+    T Q0[5];
+    compat_dev(g, Ql, Qr, Q0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ff[(kZQ0 + k) * TG::NFF + e] = Q0[k];
+      ff[(kZDn + k) * TG::NFF + e] = Dn[k];
+      ff[(kZQl + k) * TG::NFF + e] = Ql[k];
+      ff[(kZQr + k) * TG::NFF + e] = Qr[k];
+      ff[(kZDl + k) * TG::NFF + e] = Dl[k];
+      ff[(kZDr + k) * TG::NFF + e] = Dr[k];
+    }
+  }
+}
+
+// Phase 2: WENO-Z edge values along t1 of line (a, i2): the five entries
+// (a .. a+4, i2) of the patch, centred on entry (a+2, i2).
+template <typename T, int DIR>
+__device__ __forceinline__ void zrow_edges(const Geo& g, const T* ff, T* ed) {
+  using TG = ZTileGeom<DIR>;
+  const T eps = T(g.weno_eps);
+  for (int it = threadIdx.x; it < TG::NF * TG::NROW; it += 256) {
+    const int f = it / TG::NROW, r = it % TG::NROW;
+    const int a = r % TG::B, i2 = r / TG::B;
+    const T* src = ff + f * TG::NFF + i2 * TG::P + a;
+    T line[5];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) line[s] = src[s];
+    T ea, eb;
+    weno_z_edges(line, eps, g.weno_p, ea, eb);
+    ed[2 * (f * TG::NROW + r)] = ea;
+    ed[2 * (f * TG::NROW + r) + 1] = eb;
+  }
+}
+
+// Phase 3 helper: the field's value (and t2-derivative, and optionally the
+// t1-derivative) at Gauss point (sm, sl) of the face at tile position (a, t).
+template <typename T, int DIR, bool T1DER>
+__device__ __forceinline__ void zgp_field(const Geo& g, const T* ff, const T* ed, int f, int a, int t, T sm, T sl,
+                                          T& val, T& d1, T& d2, T& token) {
+  using TG = ZTileGeom<DIR>;
+  const T eps = T(g.weno_eps);
+  // one field at a time: the reads wait for the previous field's result, so the
+  // scheduler cannot interleave the fields and hold all their temporaries at once
+  zdep(a, token);
+  T rv[5], rd[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const T m = ff[f * TG::NFF + (t + r) * TG::P + a + 2];
+    const int li = f * TG::NROW + (t + r) * TG::B + a;
+    const T ea = ed[2 * li], eb = ed[2 * li + 1];
+    rv[r] = zpar_val(m, ea, eb, sm);
+    if (T1DER) rd[r] = zpar_der(m, ea, eb, sm);
+  }
+  T ea, eb;
+  weno_z_edges(rv, eps, g.weno_p, ea, eb);
+  val = zpar_val(rv[2], ea, eb, sl);
+  d2 = zpar_der(rv[2], ea, eb, sl) * T(g.inv_h[TG::A2]);
+  if (T1DER) {
+    weno_z_edges(rd, eps, g.weno_p, ea, eb);
+    d1 = zpar_val(rd[2], ea, eb, sl) * T(g.inv_h[TG::A1]);
+    token = d1;
+  } else {
+    token = val;
+  }
+}
+
+template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+__device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
+                                            const double* __restrict__ dtp, int nt1, int nt2, int nper) {
+  using TG = ZTileGeom<DIR>;
+  __shared__ T ff[TG::NF * TG::NFF];
+  __shared__ T ed[2 * TG::NF * TG::NROW];
+  const int tile = tile_of_block(nper);
+  const int Nn = g.n[DIR];
+  if (tile >= Nn * nt1 * nt2) return;  // whole workgroup leaves together
+  const int on = tile % Nn;
+  const int o1 = ((tile / Nn) % nt1) * TG::B;
+  const int o2 = (tile / (Nn * nt1)) * TG::B;
+
+  zface_field<T, DIR>(g, q, ff, on, o1, o2);
+  __syncthreads();
+  zrow_edges<T, DIR>(g, ff, ed);
+  __syncthreads();
+
+  const int tid = threadIdx.x;
+  const int face = tid >> 2, gp = tid & 3;
+  const int a = face % TG::B, t = face / TG::B;
+  const T sm = (gp & 2) ? T(1) : T(-1);  // t1 Gauss point
+  const T sl = (gp & 1) ? T(1) : T(-1);  // t2 Gauss point
+  const T dt = T(*dtp);
+  const T K = T(g.K);
+  T dum, tok = T(0);
+  // values (and t2-derivatives) of Q_l, Q_r and Q0 first: the collision time needs them
+  T Ql[5], Qr[5], Q0[5], Ql2[5], Qr2[5], Q02[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    zgp_field<T, DIR, false>(g, ff, ed, kZQl + k, a, t, sm, sl, Ql[k], dum, Ql2[k], tok);
+    zgp_field<T, DIR, false>(g, ff, ed, kZQr + k, a, t, sm, sl, Qr[k], dum, Qr2[k], tok);
+    zgp_field<T, DIR, false>(g, ff, ed, kZQ0 + k, a, t, sm, sl, Q0[k], dum, Q02[k], tok);
+  }
+  ZCoef<T> c;
+  zflux_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
+  ZAcc<T> acc;
+  {
+    T D[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      zgp_field<T, DIR, false>(g, ff, ed, kZDn + k, a, t, sm, sl, D[0][k], dum, dum, tok);
+      zgp_field<T, DIR, true>(g, ff, ed, kZQ0 + k, a, t, sm, sl, dum, D[1][k], dum, tok);
+      D[2][k] = Q02[k];
+    }
+    zside(c.s0, D, 0, K, c.eq1, c.eqh, acc, true);
+  }
+  {
+    // the next side's LDS reads wait for the previous side's result
+    int aa = a;
+    zdep(aa, acc.I1[4]);
+    T D[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      zgp_field<T, DIR, false>(g, ff, ed, kZDl + k, aa, t, sm, sl, D[0][k], dum, dum, tok);
+      zgp_field<T, DIR, true>(g, ff, ed, kZQl + k, aa, t, sm, sl, dum, D[1][k], dum, tok);
+      D[2][k] = Ql2[k];
+    }
+    zside(c.sl, D, +1, K, c.in1, c.inh, acc, false);
+  }
+  {
+    int aa = a;
+    zdep(aa, acc.I1[4]);
+    T D[3][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      zgp_field<T, DIR, false>(g, ff, ed, kZDr + k, aa, t, sm, sl, D[0][k], dum, dum, tok);
+      zgp_field<T, DIR, true>(g, ff, ed, kZQr + k, aa, t, sm, sl, dum, D[1][k], dum, tok);
+      D[2][k] = Qr2[k];
+    }
+    zside(c.sr, D, -1, K, c.in1, c.inh, acc, false);
+  }
+  T F[5], dF[5];
+  zflux_end(g, c, acc, dt, F, dF);
+  // sum of the four Gauss points (adjacent lanes), face average = sum / 4
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F[k] += __shfl_xor(F[k], 1);
+    F[k] += __shfl_xor(F[k], 2);
+    dF[k] += __shfl_xor(dF[k], 1);
+    dF[k] += __shfl_xor(dF[k], 2);
+  }
+  int cc[3];
+  cc[DIR] = on;
+  cc[TG::A1] = o1 + a;
+  cc[TG::A2] = o2 + t;
+  if (cc[TG::A1] >= g.n[TG::A1] || cc[TG::A2] >= g.n[TG::A2]) return;
+  const long long idx = (long long)cc[0] + (long long)cc[1] * g.stride[1] + (long long)cc[2] * g.stride[2];
+  // each lane of the face writes every fourth of its ten outputs
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int gk = gcomp_local<DIR>(k);
+    if (!STAGE2 && (k & 3) == gp) fl[(long long)gk * g.N + idx] = T(0.25) * F[k];
+    if (((k + 5) & 3) == gp) fl[(long long)(5 + gk) * g.N + idx] = T(0.25) * dF[k];
+  }
+}
+
+template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
+flux_z_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
+              const double* __restrict__ dtp, int nt1, int nt2, int nper) {
+  if (*stop) return;
+  flux_z_body<T, DIR, STAGE2, VAR_MU>(g, q, fl, dtp, nt1, nt2, nper);
+}
+
+template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+static void launch_z_dir(const Geo& g, const double* q, T* fl, const int* stop, const double* dtp, hipStream_t st) {
+  using TG = ZTileGeom<DIR>;
+  const int nt1 = (g.n[TG::A1] + TG::B - 1) / TG::B;
+  const int nt2 = (g.n[TG::A2] + TG::B - 1) / TG::B;
+  const int tiles = g.n[DIR] * nt1 * nt2;
+  const int nper = (tiles + 7) / 8;
+  flux_z_kernel<T, DIR, STAGE2, VAR_MU><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, dtp, nt1,
+                                                                                      nt2, nper);
+}
+
+template <typename T, bool STAGE2, bool VAR_MU>
+static void launch_z_any(const Geo& g, int dir, const double* q, T* fl, const int* stop, const double* dtp,
+                         hipStream_t st) {
+  if (dir == 0) launch_z_dir<T, 0, STAGE2, VAR_MU>(g, q, fl, stop, dtp, st);
+  else if (dir == 1) launch_z_dir<T, 1, STAGE2, VAR_MU>(g, q, fl, stop, dtp, st);
+  else launch_z_dir<T, 2, STAGE2, VAR_MU>(g, q, fl, stop, dtp, st);
+}
+
+template <typename T>
+static void launch_z_t(const Geo& g, int dir, bool stage2, const double* q, T* fl, const int* stop, const double* dtp,
+                       hipStream_t st) {
+  const bool var_mu = g.mu_exp != 0.0;
+  if (stage2) {
+    if (var_mu) launch_z_any<T, true, true>(g, dir, q, fl, stop, dtp, st);
+    else launch_z_any<T, true, false>(g, dir, q, fl, stop, dtp, st);
+  } else {
+    if (var_mu) launch_z_any<T, false, true>(g, dir, q, fl, stop, dtp, st);
+    else launch_z_any<T, false, false>(g, dir, q, fl, stop, dtp, st);
+  }
+}
+
+void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, double* fl, const int* stop,
+                   const double* dtp, hipStream_t st) {
+  launch_z_t<double>(g, dir, stage2, q, fl, stop, dtp, st);
+}
+
+void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop, const double* dtp,
+                   hipStream_t st) {
+  launch_z_t<float>(g, dir, stage2, q, fl, stop, dtp, st);
+}
+
+}  // namespace hgks

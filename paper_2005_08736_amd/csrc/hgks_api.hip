@@ -80,9 +80,11 @@ int validate(const hgks_params* p) {
   if (p->bc_y != HGKS_BC_PERIODIC && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_INVALID_ARG;
   long long N = (long long)p->nx * p->ny * p->nz;
   if (N > (1LL << 31) - 1) return HGKS_E_INVALID_ARG;  // 32-bit cell counts in the launch grids
-  // implemented so far: smooth mode on periodic boxes
-  if (p->mode != HGKS_MODE_SMOOTH || p->bc_y != HGKS_BC_PERIODIC || p->stretch_b != 0.0 || p->body_force_x != 0.0)
-    return HGKS_E_UNSUPPORTED;
+  if (p->mode == HGKS_MODE_WENOZ) {
+    if (!(p->weno_eps > 0.0) || p->weno_p < 1 || p->weno_p > 4 || !(p->c_art >= 0.0)) return HGKS_E_INVALID_ARG;
+  }
+  // implemented so far: periodic boxes
+  if (p->bc_y != HGKS_BC_PERIODIC || p->stretch_b != 0.0 || p->body_force_x != 0.0) return HGKS_E_UNSUPPORTED;
   return HGKS_OK;
 }
 
@@ -111,6 +113,9 @@ Geo make_geo(const hgks_params* p) {
   g.T_ref = p->T_ref;
   g.mu_exp = p->mu_exp;
   g.cfl = p->cfl;
+  g.weno_eps = p->weno_eps;
+  g.weno_p = p->weno_p;
+  g.c_art = p->c_art;
   g.rho_ref = 1.0;
   g.p_ref = 1.0;
   g.E_ref = g.p_ref * g.inv_gm1;
@@ -168,10 +173,14 @@ TF* fl_dir(hgks_handle* h, int d) {
 void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop) {
   for (int d = 0; d < 3; ++d) {
     bool on = prof_begin(h, stage2 ? HGKS_KCLASS_FLUX_STAGE2 : HGKS_KCLASS_FLUX_STAGE1);
-    if (f32(h))
-      launch_flux_fused(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, h->stream);
-    else
-      launch_flux_fused(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, h->stream);
+    const bool z = h->p.mode == HGKS_MODE_WENOZ;
+    if (f32(h)) {
+      if (z) launch_flux_z(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, &h->ctrl->dt, h->stream);
+      else launch_flux_fused(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, h->stream);
+    } else {
+      if (z) launch_flux_z(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, &h->ctrl->dt, h->stream);
+      else launch_flux_fused(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, h->stream);
+    }
     prof_end(h, on);
   }
 }
@@ -324,8 +333,12 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
 }
 
 int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, double* dL) {
-  (void)dt;
   if (!h || !q_in || !L || !dL) return HGKS_E_INVALID_ARG;
+  if (h->p.mode == HGKS_MODE_WENOZ) {
+    // the full flux is integrated over the step: it needs dt
+    if (!(dt > 0.0)) return HGKS_E_INVALID_ARG;
+    launch_set_dt(h->ctrl, dt, h->stream);
+  }
   all_fluxes(h, q_in, false, &h->ctrl->zero);
   if (f32(h))
     launch_operator(h->geo, fl_dir<float>(h, 0), L, dL, h->stream);
@@ -335,14 +348,20 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
 }
 
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF) {
-  (void)dt;
   if (!h || !q_in || !F || !dF || dir < 0 || dir > 2) return HGKS_E_INVALID_ARG;
   const Geo& g = h->geo;
+  const bool z = h->p.mode == HGKS_MODE_WENOZ;
+  if (z) {
+    if (!(dt > 0.0)) return HGKS_E_INVALID_ARG;
+    launch_set_dt(h->ctrl, dt, h->stream);
+  }
   if (f32(h)) {
-    launch_flux_fused(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, h->stream);
+    if (z) launch_flux_z(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, &h->ctrl->dt, h->stream);
+    else launch_flux_fused(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, h->stream);
     launch_export_flux(g, dir, fl_dir<float>(h, dir), F, dF, h->stream);
   } else {
-    launch_flux_fused(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, h->stream);
+    if (z) launch_flux_z(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, &h->ctrl->dt, h->stream);
+    else launch_flux_fused(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, h->stream);
     launch_export_flux(g, dir, fl_dir<double>(h, dir), F, dF, h->stream);
   }
   return hip_status(hipGetLastError());
@@ -351,7 +370,8 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n) {
   if (!h || !q_n || !lam_np1 || !lam_n || !(dt > 0.0)) return HGKS_E_INVALID_ARG;
   if (lam_n == lam_np1 || lam_n == q_n) return HGKS_E_INVALID_ARG;
-  if (h->p.precision != HGKS_PREC_F64 || h->p.mu_exp != 0.0) return HGKS_E_UNSUPPORTED;
+  if (h->p.precision != HGKS_PREC_F64 || h->p.mu_exp != 0.0 || h->p.mode != HGKS_MODE_SMOOTH)
+    return HGKS_E_UNSUPPORTED;
   const Geo& g = h->geo;
   hipStream_t st = h->stream;
   const long long n5 = 5 * g.N;

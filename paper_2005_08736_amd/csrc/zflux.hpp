@@ -1,0 +1,482 @@
+// Device math of the WENO-Z / full-flux mode (mode Z) of the HGKS stage update:
+// nonlinear fifth-order reconstruction with Z-type weights and the complete
+// second-order gas distribution of Eq. (flux), integrated in time (Sec. 2.1).
+// Host-and-device templates on the arithmetic type T (double for the FP64
+// path, float for the FP32-flux form).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace hgks {
+
+// Value-dependency barrier: x is treated as recomputed from `after`, so work that
+// uses x cannot be scheduled before `after` is available.  Used to keep
+// independent stages of a long computation from being interleaved by the
+// scheduler (which would keep both stages' temporaries live at once).
+template <typename T, typename U>
+__host__ __device__ __forceinline__ void zdep(T& x, const U& after) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x) : "v"(after));
+#else
+  (void)after;
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// WENO-Z on five cell averages v[0..4] (cell 2 in the middle).
+//
+// Sub-stencils of three cells with the Jiang-Shu smoothness indicators
+//   b0 = 13/12 (v0 - 2 v1 + v2)^2 + 1/4 (v0 - 4 v1 + 3 v2)^2
+//   b1 = 13/12 (v1 - 2 v2 + v3)^2 + 1/4 (v1 - v3)^2
+//   b2 = 13/12 (v2 - 2 v3 + v4)^2 + 1/4 (3 v2 - 4 v3 + v4)^2
+// and the Z weights alpha_k = d_k (1 + (tau5 / (b_k + eps))^p), tau5 = |b0 - b2|,
+// optimal weights d = (1/10, 6/10, 3/10) towards the edge being reconstructed.
+// The sub-stencil values at the right edge of cell 2 are
+//   (2 v0 - 7 v1 + 11 v2)/6, (-v1 + 5 v2 + 2 v3)/6, (2 v2 + 5 v3 - v4)/6,
+// and their derivatives there (per unit cell width) v0 - 3 v1 + 2 v2, v3 - v2,
+// v3 - v2.  The left edge is the same construction on the reversed line, whose
+// indicators are (b2, b1, b0): both edges share one set of ratios.
+// ---------------------------------------------------------------------------
+template <typename T>
+__host__ __device__ __forceinline__ T zratio(T tau5, T b, T eps, int p) {
+  T r = tau5 / (b + eps);
+  T out = r;
+  for (int i = 1; i < p; ++i) out = out * r;
+  return out;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void zbeta(const T* v, T& b0, T& b1, T& b2) {
+  const T c13 = T(13.0 / 12.0);
+  T s0 = v[0] - T(2) * v[1] + v[2], t0 = v[0] - T(4) * v[1] + T(3) * v[2];
+  T s1 = v[1] - T(2) * v[2] + v[3], t1 = v[1] - v[3];
+  T s2 = v[2] - T(2) * v[3] + v[4], t2 = T(3) * v[2] - T(4) * v[3] + v[4];
+  b0 = c13 * s0 * s0 + T(0.25) * t0 * t0;
+  b1 = c13 * s1 * s1 + T(0.25) * t1 * t1;
+  b2 = c13 * s2 * s2 + T(0.25) * t2 * t2;
+}
+
+// Value and slope (per unit width) at the right edge of the middle cell.
+template <typename T>
+__host__ __device__ __forceinline__ void weno_z_right(const T* v, T eps, int p, T& val, T& slope) {
+  T b0, b1, b2;
+  zbeta(v, b0, b1, b2);
+  T tau5 = fabs(b0 - b2);
+  T a0 = T(0.1) * (T(1) + zratio(tau5, b0, eps, p));
+  T a1 = T(0.6) * (T(1) + zratio(tau5, b1, eps, p));
+  T a2 = T(0.3) * (T(1) + zratio(tau5, b2, eps, p));
+  T sum = a0 + a1 + a2;
+  T w0 = a0 / sum, w1 = a1 / sum, w2 = a2 / sum;
+  T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
+  T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
+  T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
+  val = w0 * q0 + w1 * q1 + w2 * q2;
+  T d0 = v[0] - T(3) * v[1] + T(2) * v[2];
+  T d1 = v[3] - v[2];
+  slope = w0 * d0 + w1 * d1 + w2 * d1;
+}
+
+// Both edge values of the middle cell: ea at its left edge, eb at its right edge.
+template <typename T>
+__host__ __device__ __forceinline__ void weno_z_edges(const T* v, T eps, int p, T& ea, T& eb) {
+  T b0, b1, b2;
+  zbeta(v, b0, b1, b2);
+  T tau5 = fabs(b0 - b2);
+  T r0 = zratio(tau5, b0, eps, p), r1 = zratio(tau5, b1, eps, p), r2 = zratio(tau5, b2, eps, p);
+  {
+    T a0 = T(0.1) * (T(1) + r0), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r2);
+    T sum = a0 + a1 + a2;
+    T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
+    T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
+    T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
+    eb = (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2;
+  }
+  {
+    // reversed line (v4, v3, v2, v1, v0): indicators (b2, b1, b0)
+    T a0 = T(0.1) * (T(1) + r2), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r0);
+    T sum = a0 + a1 + a2;
+    T q0 = T(1.0 / 3.0) * v[4] - T(7.0 / 6.0) * v[3] + T(11.0 / 6.0) * v[2];
+    T q1 = T(-1.0 / 6.0) * v[3] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[1];
+    T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[1] - T(1.0 / 6.0) * v[0];
+    ea = (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2;
+  }
+}
+
+// Tangential reconstruction of mode Z inside the middle face: the parabola with
+// the face average m and the WENO-Z edge values ea, eb, evaluated at the Gauss
+// point s = sgn / (2 sqrt 3) (value) and differentiated there (per unit width):
+//   value = m + sgn (eb - ea) / (2 sqrt 3),  slope = (eb - ea) + sgn sqrt 3 (ea + eb - 2 m).
+constexpr double kGauss = 0.28867513459481288225;  // 1 / (2 sqrt 3)
+
+template <typename T>
+__host__ __device__ __forceinline__ T zpar_val(T m, T ea, T eb, T sgn) {
+  return m + sgn * (eb - ea) * T(kGauss);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T zpar_der(T m, T ea, T eb, T sgn) {
+  return (eb - ea) + sgn * T(kS3) * (ea + eb - T(2) * m);
+}
+
+// ---------------------------------------------------------------------------
+// Full gas distribution at one Gauss point (Eq. (flux)) in the local frame.
+//
+// f = (1 - e^{-t/tau}) g0 + ((t + tau) e^{-t/tau} - tau) (a.u) g0 + (t - tau + tau e^{-t/tau}) A g0
+//     + e^{-t/tau} [ -(tau + t)(a^l.u) g_l - tau A^l g_l ]_{u>0} + [same with r]_{u<0}
+// (g_l carries the Heaviside factor of u > 0, g_r that of u < 0; the zeroth-order
+// half-space parts e^{-t/tau} g_{l,r} are folded in through the coefficient of
+// <psi>).  Each part's psi-moments factor into one-dimensional Gaussian moments
+// of u, v, w and of the internal variable xi.  Time integrals over [0, delta]
+// with e = exp(-delta/tau), om = 1 - e:
+//   equilibrium side:   c_eq = delta - tau om,  c_a = 2 tau^2 om - tau delta (1 + e),
+//                       c_A = delta^2/2 - tau delta + tau^2 om,
+//   each initial side:  c_eq = tau om,  c_a = -2 tau^2 om + tau delta e,  c_A = -tau^2 om.
+// F^n and dF^n/dt follow from the integrals over [0, dt] and [0, dt/2]
+// (Eq. (expansion-1)):  F = (4 I(dt/2) - I(dt)) / dt,  dF = 4 (I(dt) - 2 I(dt/2)) / dt^2.
+// The Prandtl-number correction adds (1/Pr - 1) times the normal heat flux, about
+// the velocity of Q0, of the integrated distribution to the energy integral.
+// ---------------------------------------------------------------------------
+// Moments of one side.  The normalised Maxwellian factorises into Gaussians in u,
+// v, w and the internal variable xi; the u-moments M[n] = <u^n> are full-space or
+// half-space, the others full-space:
+//   full-space recursion  M[n] = U M[n-1] + (n-1)/(2 lambda) M[n-2],  M[0] = 1, M[1] = U;
+//   half space (sign +1: u > 0, -1: u < 0) the same recursion from
+//   M[0] = 1/2 + sign erf(sqrt(lambda) U)/2,
+//   M[1] = U M[0] + sign exp(-lambda U^2) / (2 sqrt(pi lambda)).
+// Every quantity the flux needs is <u^p P psi_k> for a polynomial P of the
+// velocity, psi = (1, u, v, w, (u^2 + s)/2) with s = v^2 + w^2 + xi^2.  Writing
+// P = sum_n u^n C_n(v, w, s), with C_n over the basis
+// (1, v, w, v^2, vw, w^2, s, vs, ws), gives
+//   <u^p P psi_0> = sum_n M[n+p] E[C_n],      <u^p P psi_1> = sum_n M[n+p+1] E[C_n],
+//   <u^p P psi_2> = sum_n M[n+p] E[v C_n],    <u^p P psi_3> = sum_n M[n+p] E[w C_n],
+//   <u^p P psi_4> = (sum_n M[n+p+2] E[C_n] + M[n+p] E[s C_n]) / 2,
+// where E is the expectation over (v, w, xi) alone:
+//   E[v^b w^c]     = V_b W_c,
+//   E[v^b w^c s]   = V_{b+2} W_c + V_b W_{c+2} + V_b W_c X_1,
+//   E[v^b w^c s^2] = V_{b+4} W_c + V_b W_{c+4} + V_b W_c X_2
+//                    + 2 (V_{b+2} W_{c+2} + V_{b+2} W_c X_1 + V_b W_{c+2} X_1),
+// with V_b = <v^b>, W_c = <w^c> (Gaussian recursions) and X_1 = <xi^2> = K/(2 lambda),
+// X_2 = <xi^4> = K (K+2)/(4 lambda^2).
+template <typename T>
+__host__ __device__ __forceinline__ void zmom_gauss(T* M, int n, T U, T i2l) {
+  M[0] = T(1);
+  M[1] = U;
+  for (int k = 2; k < n; ++k) M[k] = U * M[k - 1] + T(k - 1) * i2l * M[k - 2];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void zmom_half(T* M, T U, T lam, T i2l, T sign) {
+  const T kInvSqrtPi = T(0.56418958354775628695);
+  T sl = sqrt(lam);
+  T x = sl * U;
+  M[0] = T(0.5) + sign * T(0.5) * erf(x);
+  M[1] = U * M[0] + sign * T(0.5) * kInvSqrtPi * exp(-x * x) / sl;
+  for (int k = 2; k < 7; ++k) M[k] = U * M[k - 1] + T(k - 1) * i2l * M[k - 2];
+}
+
+template <typename T>
+struct ZGauss {
+  T v[6], w[6], x1, x2;
+  __host__ __device__ __forceinline__ T E(int b, int c, int m) const {
+    if (m == 0) return v[b] * w[c];
+    if (m == 1) return v[b + 2] * w[c] + v[b] * w[c + 2] + v[b] * w[c] * x1;
+    return v[b + 4] * w[c] + v[b] * w[c + 4] + v[b] * w[c] * x2 +
+           T(2) * (v[b + 2] * w[c + 2] + v[b + 2] * w[c] * x1 + v[b] * w[c + 2] * x1);
+  }
+};
+
+// Exponents (b, c, m) of the basis (1, v, w, v^2, vw, w^2, s, vs, ws).
+__host__ __device__ constexpr int zb_b(int i) { return (i == 1 || i == 4 || i == 7) ? 1 : (i == 3 ? 2 : 0); }
+__host__ __device__ constexpr int zb_c(int i) { return (i == 2 || i == 4 || i == 8) ? 1 : (i == 5 ? 2 : 0); }
+__host__ __device__ constexpr int zb_m(int i) { return i >= 6 ? 1 : 0; }
+
+// E[C], E[v C], E[w C], E[s C] of C = sum over the basis terms present in MASK
+// (bit i: basis term i) with coefficients c[i].
+template <int MASK, typename T>
+__host__ __device__ __forceinline__ void zexpect(const T* c, const ZGauss<T>& G, T* e) {
+  bool first = true;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (!((MASK >> i) & 1)) continue;
+    const int b = zb_b(i), cc = zb_c(i), m = zb_m(i);
+    T t1 = c[i] * G.E(b, cc, m), tv = c[i] * G.E(b + 1, cc, m), tw = c[i] * G.E(b, cc + 1, m),
+      ts = c[i] * G.E(b, cc, m + 1);
+    if (first) {
+      e[0] = t1; e[1] = tv; e[2] = tw; e[3] = ts;
+      first = false;
+    } else {
+      e[0] = e[0] + t1; e[1] = e[1] + tv; e[2] = e[2] + tw; e[3] = e[3] + ts;
+    }
+  }
+}
+
+// <u^p P psi> for p = 0 (r0) and, when BOTH, p = 1 (r1), from the expectations
+// e[n][4] of the u-power coefficients C_n, n < NC.
+template <int NC, bool BOTH, typename T>
+__host__ __device__ __forceinline__ void zrows(const T* M, const T (*e)[4], T* r0, T* r1) {
+#pragma unroll
+  for (int p = 0; p < (BOTH ? 2 : 1); ++p) {
+    T* r = p ? r1 : r0;
+    r[0] = M[p] * e[0][0];
+    r[1] = M[p + 1] * e[0][0];
+    r[2] = M[p] * e[0][1];
+    r[3] = M[p] * e[0][2];
+    T e4 = M[p + 2] * e[0][0] + M[p] * e[0][3];
+#pragma unroll
+    for (int n = 1; n < NC; ++n) {
+      r[0] = r[0] + M[n + p] * e[n][0];
+      r[1] = r[1] + M[n + p + 1] * e[n][0];
+      r[2] = r[2] + M[n + p] * e[n][1];
+      r[3] = r[3] + M[n + p] * e[n][2];
+      e4 = e4 + M[n + p + 2] * e[n][0] + M[n + p] * e[n][3];
+    }
+    r[4] = T(0.5) * e4;
+  }
+}
+
+// Expectations of the slope polynomial a_n u + a_t1 v + a_t2 w ... in the form
+// u (phi_n) + v (phi_t1) + w (phi_t2), phi_X = X0 + X1 u + X2 v + X3 w + X4 (u^2 + s)/2:
+//   C_0 = t0 v + t2 v^2 + (t3 + r2) vw + t4/2 vs + r0 w + r3 w^2 + r4/2 ws
+//   C_1 = n0 + (n2 + t1) v + (n3 + r1) w + n4/2 s
+//   C_2 = n1 + t4/2 v + r4/2 w
+//   C_3 = n4/2
+// (n = a_n, t = a_t1, r = a_t2).
+template <typename T>
+__host__ __device__ __forceinline__ void zexpect_slopes(const T (*a)[5], const ZGauss<T>& G, T (*e)[4]) {
+  const T* n = a[0];
+  const T* t = a[1];
+  const T* r = a[2];
+  {
+    T c[9] = {T(0), t[0], r[0], t[2], t[3] + r[2], r[3], T(0), T(0.5) * t[4], T(0.5) * r[4]};
+    zexpect<0x1BE>(c, G, e[0]);
+  }
+  {
+    T c[9] = {n[0], n[2] + t[1], n[3] + r[1], T(0), T(0), T(0), T(0.5) * n[4], T(0), T(0)};
+    zexpect<0x047>(c, G, e[1]);
+  }
+  {
+    T c[9] = {n[1], T(0.5) * t[4], T(0.5) * r[4], T(0), T(0), T(0), T(0), T(0), T(0)};
+    zexpect<0x007>(c, G, e[2]);
+  }
+  {
+    T c[9] = {T(0.5) * n[4], T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    zexpect<0x001>(c, G, e[3]);
+  }
+}
+
+// Expectations of phi_A = A0 + A1 u + A2 v + A3 w + A4 (u^2 + s)/2:
+//   C_0 = A0 + A2 v + A3 w + A4/2 s,  C_1 = A1,  C_2 = A4/2.
+template <typename T>
+__host__ __device__ __forceinline__ void zexpect_phi(const T* A, const ZGauss<T>& G, T (*e)[4]) {
+  {
+    T c[9] = {A[0], A[2], A[3], T(0), T(0), T(0), T(0.5) * A[4], T(0), T(0)};
+    zexpect<0x047>(c, G, e[0]);
+  }
+  {
+    T c[9] = {A[1], T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    zexpect<0x001>(c, G, e[1]);
+  }
+  {
+    T c[9] = {T(0.5) * A[4], T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    zexpect<0x001>(c, G, e[2]);
+  }
+}
+
+// Slope polynomial a with <a psi> = b for a Maxwellian (U, V, W, lambda): the
+// 5 x 5 system of Gaussian moments solved in closed form.
+template <typename T>
+__host__ __device__ __forceinline__ void zslope(const T* b, T U, T V, T W, T lam, T K, T* a) {
+  T Ep = T(0.5) * (U * U + V * V + W * W + (K + T(3)) / (T(2) * lam));
+  T B = b[1] - U * b[0], C = b[2] - V * b[0], D = b[3] - W * b[0];
+  a[4] = T(8) * lam * lam / (K + T(3)) * (b[4] - Ep * b[0] - U * B - V * C - W * D);
+  a[1] = T(2) * lam * B - U * a[4];
+  a[2] = T(2) * lam * C - V * a[4];
+  a[3] = T(2) * lam * D - W * a[4];
+  a[0] = b[0] - U * a[1] - V * a[2] - W * a[3] - Ep * a[4];
+}
+
+// Primitive variables of a local-frame deviation state.
+template <typename T>
+struct ZPrim {
+  T rho, U, V, W, p, lam;
+};
+template <typename T>
+__host__ __device__ __forceinline__ ZPrim<T> zprim(const Geo& g, const T* dQ) {
+  ZPrim<T> s;
+  s.rho = T(g.rho_ref) + dQ[0];
+  T ir = T(1) / s.rho;
+  s.U = dQ[1] * ir;
+  s.V = dQ[2] * ir;
+  s.W = dQ[3] * ir;
+  s.p = T(g.p_ref) + T(g.gm1) * (dQ[4] - T(0.5) * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
+  s.lam = T(0.5) * s.rho / s.p;
+  return s;
+}
+
+// Time-integral coefficients over [0, delta]: eq[0..2] for the equilibrium side,
+// in[0..2] for the two initial sides.
+template <typename T>
+__host__ __device__ __forceinline__ void ztime(T delta, T tau, T* eq, T* in) {
+  T e = exp(-delta / tau);
+  T om = T(1) - e;
+  eq[0] = delta - tau * om;
+  eq[1] = T(2) * tau * tau * om - tau * delta * (T(1) + e);
+  eq[2] = T(0.5) * delta * delta - tau * delta + tau * tau * om;
+  in[0] = tau * om;
+  in[1] = T(-2) * tau * tau * om + tau * delta * e;
+  in[2] = -tau * tau * om;
+}
+
+// Accumulated time integrals: I = flux moments (<u ...>), J = density moments,
+// for delta = dt (suffix 1) and delta = dt/2 (suffix h).
+template <typename T>
+struct ZAcc {
+  T I1[5], J1[5], Ih[5], Jh[5];
+};
+
+// One side of the distribution: its Maxwellian (s), its spatial slopes D[3][5]
+// (local frame, along n, t1, t2), half = 0 (equilibrium, full space), +1 or -1.
+// Adds rho (c0 <u^p psi> + c1 <u^p (a.u) psi> + c2 <u^p A psi>) for p = 1 (I)
+// and p = 0 (J) with the coefficient sets k1 (delta = dt) and kh (dt/2); the
+// time slope A solves <a.u + A> = 0 over the side's full-space Maxwellian.
+template <typename T>
+__host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* k1,
+                                               const T* kh, ZAcc<T>& acc, bool first) {
+  const T i2l = T(0.5) / s.lam;
+  ZGauss<T> G;
+  zmom_gauss(G.v, 6, s.V, i2l);
+  zmom_gauss(G.w, 6, s.W, i2l);
+  G.x1 = K * i2l;
+  G.x2 = K * (K + T(2)) * i2l * i2l;
+  T M[7];
+  zmom_gauss(M, 7, s.U, i2l);
+  T a[3][5];
+  const T ir = T(1) / s.rho;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T b[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) b[k] = D[d][k] * ir;
+    zslope(b, s.U, s.V, s.W, s.lam, K, a[d]);
+  }
+  T ea[4][4];
+  zexpect_slopes(a, G, ea);
+  T ra0[5], ra1[5];
+  zrows<4, false>(M, ea, ra0, ra1);  // <(a.u) psi>, full space
+  T A[5];
+  {
+    T bt[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) bt[k] = -ra0[k];
+    zslope(bt, s.U, s.V, s.W, s.lam, K, A);
+  }
+  if (half != 0) {
+    zmom_half(M, s.U, s.lam, i2l, T(half));
+    zrows<4, true>(M, ea, ra0, ra1);
+  } else {
+    zrows<4, true>(M, ea, ra0, ra1);
+  }
+  T eA[3][4];
+  zexpect_phi(A, G, eA);
+  T rA0[5], rA1[5];
+  zrows<3, true>(M, eA, rA0, rA1);
+  // phi = 1: C_0 = 1
+  T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
+  T r10[5], r11[5];
+  zrows<1, true>(M, e1, r10, r11);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    T j1 = s.rho * (k1[0] * r10[k] + k1[1] * ra0[k] + k1[2] * rA0[k]);
+    T jh = s.rho * (kh[0] * r10[k] + kh[1] * ra0[k] + kh[2] * rA0[k]);
+    T i1 = s.rho * (k1[0] * r11[k] + k1[1] * ra1[k] + k1[2] * rA1[k]);
+    T ih = s.rho * (kh[0] * r11[k] + kh[1] * ra1[k] + kh[2] * rA1[k]);
+    acc.J1[k] = first ? j1 : acc.J1[k] + j1;
+    acc.Jh[k] = first ? jh : acc.Jh[k] + jh;
+    acc.I1[k] = first ? i1 : acc.I1[k] + i1;
+    acc.Ih[k] = first ? ih : acc.Ih[k] + ih;
+  }
+}
+
+// Normal heat flux of a perturbation with flux moments G1 and density moments G0
+// about the velocity (U, V, W):  h(G1) - U h(G0),
+// h(G) = G4 - (U G1 + V G2 + W G3) + |U|^2 G0 / 2.
+template <typename T>
+__host__ __device__ __forceinline__ T zheat(const T* G1, const T* G0, T U, T V, T W) {
+  T k = T(0.5) * (U * U + V * V + W * W);
+  T h1 = G1[4] - (U * G1[1] + V * G1[2] + W * G1[3]) + k * G1[0];
+  T h0 = G0[4] - (U * G0[1] + V * G0[2] + W * G0[3]) + k * G0[0];
+  return h1 - U * h0;
+}
+
+// Full flux at one Gauss point, in three parts so that a kernel can reconstruct
+// each side's slopes just before they are used.
+//   zflux_begin: primitive states, collision time
+//     tau = mu(T0)/p0 + c_art |p_l - p_r| / (p_l + p_r) dt  (Sec. 3)
+//     and the time-integral coefficients for dt and dt/2;
+//   zside (above) for the equilibrium side and the two initial sides;
+//   zflux_end: Prandtl-number correction and F^n, dF^n/dt.
+// Inputs (local frame): deviations of Q0, Q_l, Q_r from the reference state and
+// their derivatives along (n, t1, t2); dt is the step.  F gets F^n without the
+// constant p_ref in its normal-momentum component, dF gets dF^n/dt.
+template <typename T>
+struct ZCoef {
+  ZPrim<T> s0, sl, sr;
+  T eq1[3], in1[3], eqh[3], inh[3];
+};
+
+template <bool VAR_MU, typename T>
+__host__ __device__ __forceinline__ void zflux_begin(const Geo& g, const T* dQ0, const T* dQl, const T* dQr, T dt,
+                                                     ZCoef<T>& c) {
+  c.s0 = zprim(g, dQ0);
+  c.sl = zprim(g, dQl);
+  c.sr = zprim(g, dQr);
+  T T0 = c.s0.p / c.s0.rho;
+  T mu = T(g.mu_ref);
+  if (VAR_MU) mu = mu * pow(T0 / T(g.T_ref), T(g.mu_exp));
+  T tau = mu / c.s0.p + T(g.c_art) * fabs((c.sl.p - c.sr.p) / (c.sl.p + c.sr.p)) * dt;
+  ztime(dt, tau, c.eq1, c.in1);
+  ztime(T(0.5) * dt, tau, c.eqh, c.inh);
+}
+
+// The same with a given collision time.
+template <typename T>
+__host__ __device__ __forceinline__ void zflux_begin_tau(const Geo& g, const T* dQ0, const T* dQl, const T* dQr,
+                                                         T tau, T dt, ZCoef<T>& c) {
+  c.s0 = zprim(g, dQ0);
+  c.sl = zprim(g, dQl);
+  c.sr = zprim(g, dQr);
+  ztime(dt, tau, c.eq1, c.in1);
+  ztime(T(0.5) * dt, tau, c.eqh, c.inh);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>& c, ZAcc<T>& acc, T dt, T* F, T* dF) {
+  const T fix = T(g.pr_fix);
+  acc.I1[4] = acc.I1[4] + fix * zheat(acc.I1, acc.J1, c.s0.U, c.s0.V, c.s0.W);
+  acc.Ih[4] = acc.Ih[4] + fix * zheat(acc.Ih, acc.Jh, c.s0.U, c.s0.V, c.s0.W);
+  const T idt = T(1) / dt;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F[k] = (T(4) * acc.Ih[k] - acc.I1[k]) * idt;
+    dF[k] = T(4) * (acc.I1[k] - T(2) * acc.Ih[k]) * idt * idt;
+  }
+  F[1] = F[1] - T(g.p_ref);
+}
+
+// Full flux with a given collision time (host checks of the device math).
+template <typename T>
+__host__ __device__ __forceinline__ void full_flux_tau(const Geo& g, const T* dQ0, const T (*D0)[5], const T* dQl,
+                                                       const T (*Dl)[5], const T* dQr, const T (*Dr)[5], T tau, T dt,
+                                                       T* F, T* dF) {
+  const T K = T(g.K);
+  ZCoef<T> c;
+  zflux_begin_tau(g, dQ0, dQl, dQr, tau, dt, c);
+  ZAcc<T> acc;
+  zside(c.s0, D0, 0, K, c.eq1, c.eqh, acc, true);
+  zdep(c.sl.rho, acc.I1[4]);
+  zside(c.sl, Dl, +1, K, c.in1, c.inh, acc, false);
+  zdep(c.sr.rho, acc.I1[4]);
+  zside(c.sr, Dr, -1, K, c.in1, c.inh, acc, false);
+  zflux_end(g, c, acc, dt, F, dF);
+}
+
+}  // namespace hgks

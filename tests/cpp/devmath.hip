@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "../../paper_2005_08736_amd/csrc/adjoint_common.hpp"
+#include "../../paper_2005_08736_amd/csrc/zflux.hpp"
 
 using namespace hgks;
 
@@ -77,6 +78,45 @@ int dm_compat_vjp(const double* Ql, const double* Qr, double gamma, double rho_r
   double lb[5] = {0, 0, 0, 0, 0}, rb[5] = {0, 0, 0, 0, 0};
   compat_dev_vjp(g, l, r, Q0b, lb, rb);
   for (int k = 0; k < 5; ++k) { Qlb[k] = lb[k]; Qrb[k] = rb[k]; }
+  return 0;
+}
+
+// WENO-Z value and slope at the right edge of the middle of v[0..4]
+int dm_weno_z_right(const double* v, double eps, int p, double* val, double* slope) {
+  weno_z_right(v, eps, p, *val, *slope);
+  return 0;
+}
+
+// WENO-Z edge values of the middle of v[0..4]
+int dm_weno_z_edges(const double* v, double eps, int p, double* ea, double* eb) {
+  weno_z_edges(v, eps, p, *ea, *eb);
+  return 0;
+}
+
+// Full flux at one Gauss point with a given collision time; states are full
+// (local frame), derivatives D[a*5+k]; F excludes p_ref in F[1]
+int dm_full_flux(const double* Ql, const double* Dl, const double* Qr, const double* Dr, const double* Q0,
+                 const double* D0, double tau, double dt, double gamma, double prandtl, double rho_ref, double p_ref,
+                 double* F, double* dF) {
+  Geo g = make(gamma, prandtl, 0.0, rho_ref, p_ref);
+  auto dev = [&](const double* Q, double* d) {
+    d[0] = Q[0] - rho_ref;
+    d[1] = Q[1];
+    d[2] = Q[2];
+    d[3] = Q[3];
+    d[4] = Q[4] - g.E_ref;
+  };
+  double l[5], r[5], z[5], dl[3][5], dr[3][5], dz[3][5];
+  dev(Ql, l);
+  dev(Qr, r);
+  dev(Q0, z);
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 5; ++k) {
+      dl[a][k] = Dl[a * 5 + k];
+      dr[a][k] = Dr[a * 5 + k];
+      dz[a][k] = D0[a * 5 + k];
+    }
+  full_flux_tau(g, z, dz, l, dl, r, dr, tau, dt, F, dF);
   return 0;
 }
 

@@ -9,7 +9,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cpp", "devmath.hip")
 LIB = os.path.join(HERE, "cpp", "libdevmath.so")
-HDRS = [os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", n) for n in ("device_common.hpp", "adjoint_common.hpp")]
+HDRS = [os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", n)
+        for n in ("device_common.hpp", "adjoint_common.hpp", "zflux.hpp")]
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -65,3 +66,25 @@ def compat_vjp(Ql, Qr, gamma, rho_ref, p_ref, Q0b):
     lib().dm_compat_vjp(_p(Ql), _p(Qr), ctypes.c_double(gamma), ctypes.c_double(rho_ref), ctypes.c_double(p_ref),
                         _p(Q0b), _p(Qlb), _p(Qrb))
     return Qlb, Qrb
+
+
+def weno_z_right(v, eps=1e-6, p=2):
+    v = _a(v, 5)
+    val, slope = np.zeros(1), np.zeros(1)
+    lib().dm_weno_z_right(_p(v), ctypes.c_double(eps), ctypes.c_int(p), _p(val), _p(slope))
+    return float(val[0]), float(slope[0])
+
+
+def weno_z_edges(v, eps=1e-6, p=2):
+    v = _a(v, 5)
+    ea, eb = np.zeros(1), np.zeros(1)
+    lib().dm_weno_z_edges(_p(v), ctypes.c_double(eps), ctypes.c_int(p), _p(ea), _p(eb))
+    return float(ea[0]), float(eb[0])
+
+
+def full_flux(Ql, Dl, Qr, Dr, Q0, D0, tau, dt, gamma, prandtl, rho_ref, p_ref):
+    args = [_a(Ql, 5), _a(Dl, 15), _a(Qr, 5), _a(Dr, 15), _a(Q0, 5), _a(D0, 15)]
+    F, dF = np.zeros(5), np.zeros(5)
+    lib().dm_full_flux(*[_p(a) for a in args], ctypes.c_double(tau), ctypes.c_double(dt), ctypes.c_double(gamma),
+                       ctypes.c_double(prandtl), ctypes.c_double(rho_ref), ctypes.c_double(p_ref), _p(F), _p(dF))
+    return F, dF

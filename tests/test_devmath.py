@@ -84,3 +84,41 @@ def test_compat_vjp_matches_central_differences(p_level):
         lhs = float(np.concatenate([Qlb, Qrb]) @ v)
         rhs = _fd_check(f, x, v, Q0b, 1e-6 * max(1.0, np.abs(x).max()))
         assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+def test_device_weno_z_matches_oracle(oracle_mod):
+    """WENO-Z value/slope and both edge values against the oracle's WENO5 with Z
+    weights: smooth, steep and discontinuous lines, exponents 1 and 2."""
+    lines = [rng.normal(size=5) for _ in range(30)]
+    lines += [np.array([1.0, 1.0, 1.0, 0.0, 0.0]), np.array([0.0, 0.0, 5.0, 5.0, 5.0]),
+              1.0 + 1e-4 * np.sin(0.3 * np.arange(5)), np.full(5, 2.5)]
+    for v in lines:
+        for p in (1, 2):
+            val, slope = devmath.weno_z_right(v, 1e-6, p)
+            rv, rs = oracle_mod.weno5(v, False, 1e-6, p)
+            sc = np.abs(v).max()
+            assert abs(val - rv) <= 1e-14 * sc and abs(slope - rs) <= 1e-13 * sc
+            ea, eb = devmath.weno_z_edges(v, 1e-6, p)
+            assert abs(eb - rv) <= 1e-14 * sc
+            assert abs(ea - oracle_mod.weno5(v[::-1].copy(), False, 1e-6, p)[0]) <= 1e-14 * sc
+
+
+@pytest.mark.parametrize("p_level", [1.0, 2.86, 71.4])
+def test_device_full_flux_matches_oracle(oracle_mod, p_level):
+    """The full flux (three Maxwellians, time integrals over dt and dt/2, Prandtl
+    correction) against the oracle at random states and slopes, dt/tau from
+    0.05 to 20."""
+    rho_ref, p_ref = 1.0, p_level
+    for i in range(24):
+        Ql, Qr = states(p_level), states(p_level)
+        Q0 = 0.5 * (Ql + Qr)
+        Dl, Dr, D0 = rng.normal(size=15), rng.normal(size=15), rng.normal(size=15)
+        tau = 1e-3 * (1 + rng.random())
+        dt = tau * [0.05, 1.0, 5.0, 20.0][i % 4]
+        F, dF = devmath.full_flux(Ql, Dl, Qr, Dr, Q0, D0, tau, dt, GAMMA, 0.72, rho_ref, p_ref)
+        F[1] += p_ref
+        rF, rdF = oracle_mod.gp_flux_full(Ql, Dl, Qr, Dr, Q0, D0, tau, dt, GAMMA, 0.72)
+        assert np.abs(F - rF).max() <= 2e-13 * np.abs(rF).max(), (F, rF)
+        # dF is a second difference of the time integrals: both sides round at
+        # ~1e-16 |I| / (dt |dF|) relative
+        assert np.abs(dF - rdF).max() <= 1e-10 * np.abs(rdF).max(), (dF, rdF)
