@@ -57,6 +57,10 @@ enum { HGKS_MODE_SMOOTH = 0, HGKS_MODE_WENOZ = 1 };
  * HGKS_PREC_F32FLUX: reconstruction and flux arithmetic in FP32 around FP64
  *   anchors, FP64 state and compensated accumulation of the flux divergence. */
 enum { HGKS_PREC_F64 = 0, HGKS_PREC_F32FLUX = 1 };
+/* HGKS_BC_WALL_ISOTHERMAL: no-slip isothermal walls at both ends of y (the
+ * channel of Sec. 3.3), closed by ghost cells mirroring the first three rows:
+ * velocity reversed, equal pressure, temperature 2 T_wall - T (at least
+ * T_wall / 2).  Smooth mode only (HGKS_E_UNSUPPORTED in mode Z). */
 enum { HGKS_BC_PERIODIC = 0, HGKS_BC_WALL_ISOTHERMAL = 1 /* y only */ };
 
 /* Number of doubles written by hgks_diagnostics. */
@@ -66,14 +70,18 @@ typedef struct {
   int32_t nx, ny, nz;      /* cells per axis; >= 6 on every periodic axis */
   double lx, ly, lz;       /* box lengths (channel: ly = 2, y in [-1, 1]) */
   int32_t bc_y;            /* HGKS_BC_* for the y axis; x and z are periodic */
-  double stretch_b;        /* 0: uniform y; > 0: tanh map of Sec. 3.3 with b_g */
+  double stretch_b;        /* 0: uniform y; > 0: tanh map y = tanh(b (eta/(1.5 pi) - 1))/tanh b,
+                              eta uniform on [0, 3 pi] (Sec. 3.3; needs walls; ly unused) */
   double gamma, prandtl;   /* specific-heat ratio (> 1) and Prandtl number (> 0) */
   double mu_ref, T_ref, mu_exp; /* mu(T) = mu_ref (T/T_ref)^mu_exp (Sec. 3.4) */
   int32_t mode;            /* HGKS_MODE_* */
   double cfl;              /* dt = cfl * min_cells min_d dx_d / (|U_d| + c) */
   double c_art, weno_eps;  /* artificial collision-time constant C (Sec. 3), WENO-Z epsilon */
   int32_t weno_p;          /* WENO-Z exponent */
-  double T_wall, body_force_x; /* channel wall temperature; constant body force f_x (Sec. 3.3) */
+  double T_wall, body_force_x; /* wall temperature (> 0 with walls); constant streamwise body
+                                  force f_x added after each step by the trapezoidal rule
+                                  (Sec. 3.3): (rho U) += dt/2 (rho^{n+1} + rho^n) f_x,
+                                  (rho E) += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x */
   int32_t precision;       /* HGKS_PREC_* */
 } hgks_params;
 
@@ -108,8 +116,10 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
 
 /* Face fluxes of direction dir (0 = x, 1 = y, 2 = z) of the state q_in: F^n and
  * dF^n/dt averaged over the face (divide-by-area form: 1/4 sum over the Gauss
- * points), global frame, face n+1/2 stored at the index of cell n.  Device
- * [5][nz][ny][nx] each.  dt as for hgks_operator.  A parity aid; no
+ * points; with a stretched y, faces having y as a tangential axis weight their
+ * Gauss points by their share of the row height), global frame, face n+1/2
+ * stored at the index of cell n (with walls, the bottom wall face of row -1/2 is
+ * not exported).  Device [5][nz][ny][nx] each.  dt as for hgks_operator.  A parity aid; no
  * synchronization. */
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF);
 
@@ -122,7 +132,8 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
  * reconstruction, compatibility state) and of the stage formulas.  Device
  * atomics accumulate the cell cotangents, so repeated calls agree to rounding,
  * not bitwise.  Smooth mode with constant viscosity and FP64 arithmetic;
- * HGKS_E_UNSUPPORTED otherwise (mode Z, mu(T), the FP32-flux form).  Enqueued on the handle's stream, no
+ * HGKS_E_UNSUPPORTED otherwise (mode Z, mu(T), the FP32-flux form, walls,
+ * stretching, body force).  Enqueued on the handle's stream, no
  * synchronization; the bound state is not touched. */
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
 

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
   tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
   const int tid = threadIdx.x;
 
-  face_field_tile<T, DIR>(g, q, ff, x0, y0, z0);
+  face_field_tile<T, DIR>(g, q, ff, x0, y0, z0, g.inv_h[DIR]);
   for (int e = tid; e < 10 * TG::NFF; e += 256) ffb[e] = T(0);
   __syncthreads();
 
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
 #pragma unroll 1
       for (int m = 0; m < 2; ++m) {
         T Qg[2][5], Dg[2][3][5];
-        gp_data<T, DIR>(ff, corner, m, i1, i2, Qg, Dg);
+        gp_data<T, DIR>(ff, corner, m, i1, i2, i2, Qg, Dg);
         T Qgb[2][5], Dgb[2][3][5];
 #pragma unroll
         for (int l = 0; l < 2; ++l) {

@@ -33,7 +33,72 @@ struct Geo {
   // WENO-Z / full-flux mode: Z-weight epsilon and exponent, artificial collision-time coefficient
   double weno_eps, c_art;
   int weno_p;
+  // channel (Sec. 3.3): isothermal no-slip walls at both ends of y, the tanh
+  // mesh in y (metric tables in device memory, see ym_* below), and the
+  // constant streamwise body force
+  int wall_y, stretch_y;
+  double T_wall, fx;
+  const double* ym;        // metric tables (stretched y only)
+  const void* fwall;       // face fluxes of the bottom wall faces (walls only), [10][nz][nx]
 };
+
+// ---------------------------------------------------------------------------
+// Stretched wall-normal mesh y(eta), eta uniform with spacing h[1] (Sec. 3.3).
+// Tables of 7 ny + 1 doubles, computed on the host at init:
+//   [0, ny)          1 / dy_j            (dy_j: height of row j)
+//   [ny, 2ny)        dy_j
+//   [2ny, 3ny+1)     1 / (y'(eta_f) h)   at the faces eta_f = f h, f = 0..ny
+//   [3ny+1, 5ny+1)   1 / (y'(eta) h)     at the two Gauss points of row j (2j + m)
+//   [5ny+1, 7ny+1)   y'(eta) h / dy_j    the Gauss points' share of the row height
+// A derivative per unit eta-width times 1/(y' h) is the physical derivative; the
+// face average of a face with y as a tangential axis weights its Gauss points
+// by their share of the row height (the two shares sum to 2 up to the
+// quadrature error of the two-point rule).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ double ym_inv_dy(const Geo& g, int j) { return g.ym[j]; }
+__host__ __device__ __forceinline__ double ym_dy(const Geo& g, int j) { return g.ym[g.n[1] + j]; }
+__host__ __device__ __forceinline__ double ym_face_inv(const Geo& g, int f) { return g.ym[2 * g.n[1] + f]; }
+__host__ __device__ __forceinline__ double ym_gp_inv(const Geo& g, int j, int m) { return g.ym[3 * g.n[1] + 1 + 2 * j + m]; }
+__host__ __device__ __forceinline__ double ym_gp_w(const Geo& g, int j, int m) { return g.ym[5 * g.n[1] + 1 + 2 * j + m]; }
+constexpr int kYmTableDoubles = 7;  // per row, plus one
+
+// Ghost state behind an isothermal no-slip wall from its mirror cell Q (global
+// frame, full conservative variables): velocity reversed, equal pressure,
+// temperature reflected about the wall temperature, T_g = 2 T_w - T, held at
+// T_w / 2 or above.
+__host__ __device__ __forceinline__ void wall_ghost(const Geo& g, double* Q) {
+  const double rho = Q[0];
+  const double U = Q[1] / rho, V = Q[2] / rho, W = Q[3] / rho;
+  const double p = g.gm1 * (Q[4] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / rho);
+  double Tg = 2.0 * g.T_wall - p / rho;
+  if (Tg < 0.5 * g.T_wall) Tg = 0.5 * g.T_wall;
+  const double rg = p / Tg;
+  Q[0] = rg;
+  Q[1] = rg * -U;
+  Q[2] = rg * -V;
+  Q[3] = rg * -W;
+  Q[4] = p / g.gm1 + 0.5 * rg * (U * U + V * V + W * W);
+}
+
+// The conservative variables of cell (x, y, z), global frame; with walls in y a
+// row outside [0, ny) is the ghost of its mirror row (-1 - y below, 2 ny - 1 - y
+// above).  x and z are in range.
+__host__ __device__ __forceinline__ void load_cell_wall(const Geo& g, const double* q, int x, int y, int z,
+                                                        double* Q) {
+  int ym = y;
+  bool ghost = false;
+  if (y < 0) {
+    ym = -1 - y;
+    ghost = true;
+  } else if (y >= g.n[1]) {
+    ym = 2 * g.n[1] - 1 - y;
+    ghost = true;
+  }
+  const long long idx = (long long)x + (long long)ym * g.stride[1] + (long long)z * g.stride[2];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];
+  if (ghost) wall_ghost(g, Q);
+}
 
 // Control block at the head of the workspace.
 constexpr int kDtHist = 1024;

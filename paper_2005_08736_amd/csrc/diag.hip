@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(Geo g, const
   double acc[kNDiag];
 #pragma unroll
   for (int s = 0; s < kNDiag; ++s) acc[s] = is_min_slot(s) ? 1e300 : 0.0;
-  const double V = g.h[0] * g.h[1] * g.h[2];
+  const double Vu = g.h[0] * g.h[1] * g.h[2];
   const double mean_rho = pass == 1 ? out[19] : 0.0;
   const double c6[3] = {45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0};  // antisymmetric weights at offsets 1, 2, 3
   for (long long idx = (long long)blockIdx.x * kDiagThreads + threadIdx.x; idx < g.N;
@@ -39,16 +39,18 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(Geo g, const
     double Q[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];
-    if (pass == 1) {
-      double dr = Q[0] - mean_rho;
-      acc[A_VAR] += dr * dr * V;
-      continue;
-    }
     int c[3];
     c[0] = int(idx % g.n[0]);
     long long r = idx / g.n[0];
     c[1] = int(r % g.n[1]);
     c[2] = int(r / g.n[1]);
+    // cell volume (row height on a stretched mesh)
+    const double V = g.stretch_y ? g.h[0] * g.h[2] * ym_dy(g, c[1]) : Vu;
+    if (pass == 1) {
+      double dr = Q[0] - mean_rho;
+      acc[A_VAR] += dr * dr * V;
+      continue;
+    }
     double ir = 1.0 / Q[0];
     double U[3] = {Q[1] * ir, Q[2] * ir, Q[3] * ir};
     double u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
@@ -68,8 +70,11 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(Geo g, const
     acc[A_MINP] = fmin(acc[A_MINP], p);
     double sp = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) sp = fmax(sp, (fabs(U[a]) + cs) * g.inv_h[a]);
+    for (int a = 0; a < 3; ++a)
+      sp = fmax(sp, (fabs(U[a]) + cs) * (a == 1 && g.stretch_y ? ym_inv_dy(g, c[1]) : g.inv_h[a]));
     acc[A_MAXS] = fmax(acc[A_MAXS], sp);
+    // the derivative diagnostics need a uniform mesh
+    if (g.stretch_y) continue;
     // velocity gradient gr[a][k] = dU_k/dx_a by the sixth-order central difference
     double gr[3][3];
 #pragma unroll
@@ -78,6 +83,15 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(Geo g, const
       double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int o = 1; o <= 3; ++o) {
+        if (a == 1 && g.wall_y && (c[1] - o < 0 || c[1] + o >= g.n[1])) {
+          // a wall within reach: neighbours beyond it are wall ghosts
+          double Qp[5], Qm[5];
+          load_cell_wall(g, q, c[0], c[1] + o, c[2], Qp);
+          load_cell_wall(g, q, c[0], c[1] - o, c[2], Qm);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) s[k] += c6[o - 1] * (Qp[1 + k] / Qp[0] - Qm[1 + k] / Qm[0]);
+          continue;
+        }
         long long ip = base + (long long)wrapi(c[a] + o, g.n[a]) * g.stride[a];
         long long im = base + (long long)wrapi(c[a] - o, g.n[a]) * g.stride[a];
         double irp = 1.0 / q[ip], irm = 1.0 / q[im];

@@ -19,7 +19,7 @@
 
 namespace hgks {
 
-template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN>
 __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                                 int ntx, int nty, int ntz, int nper) {
   using TG = TileGeom<DIR>;
@@ -28,8 +28,12 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
   tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
+  // channel: y-face rows run from the bottom wall face (row -1) to the top one
+  if (CHAN && DIR == 1) y0 -= 1;
+  double dn_scale = g.inv_h[DIR];
+  if (CHAN && DIR == 1 && g.stretch_y) dn_scale = ym_face_inv(g, y0 + 1);
 
-  face_field_tile<T, DIR>(g, q, ff, x0, y0, z0);
+  face_field_tile<T, DIR, CHAN>(g, q, ff, x0, y0, z0, dn_scale);
   __syncthreads();
 
   const int tid = threadIdx.x;
@@ -39,29 +43,53 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
   const int centre = (fx + TG::HX) + (fy + TG::HY) * TG::FX + (fz + TG::HZ) * TG::FX * TG::FY;
   const int corner = centre - 2 * TG::S[A1] - 2 * TG::S[A2];
-  const T i1 = T(g.inv_h[A1]), i2 = T(g.inv_h[A2]);
+  // metric factors of the tangential derivatives and Gauss weights: y is t1 of
+  // x-faces and t2 of z-faces
+  const bool ys = CHAN && DIR != 1 && g.stretch_y;
+  T i2m = T(g.inv_h[A2]), i2p = i2m, w2m = T(1), w2p = T(1);
+  if (ys && DIR == 2) {
+    i2m = T(ym_gp_inv(g, gy, 0));
+    i2p = T(ym_gp_inv(g, gy, 1));
+    w2m = T(ym_gp_w(g, gy, 0));
+    w2p = T(ym_gp_w(g, gy, 1));
+  }
   T Fs[5] = {0, 0, 0, 0, 0}, dFs[5] = {0, 0, 0, 0, 0};
 #pragma unroll 1
   for (int m = 0; m < 2; ++m) {  // t1 Gauss point (-, +)
+    T i1 = T(g.inv_h[A1]), w1 = T(1);
+    if (ys && DIR == 0) {
+      i1 = T(ym_gp_inv(g, gy, m));
+      w1 = T(ym_gp_w(g, gy, m));
+    }
     T Qg[2][5], Dg[2][3][5];
-    gp_data<T, DIR>(ff, corner, m, i1, i2, Qg, Dg);
+    gp_data<T, DIR>(ff, corner, m, i1, i2m, i2p, Qg, Dg);
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
       T F[5], dF[5];
       smooth_flux<!STAGE2, VAR_MU>(g, Qg[l], Dg[l], F, dF);
+      const T w = ys ? w1 * (l ? w2p : w2m) : T(1);
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        if (!STAGE2) Fs[k] += F[k];
-        dFs[k] += dF[k];
+        if (!STAGE2) Fs[k] += ys ? w * F[k] : F[k];
+        dFs[k] += ys ? w * dF[k] : dF[k];
       }
     }
   }
-  const long long idx = (long long)gx + (long long)gy * g.stride[1] + (long long)gz * g.stride[2];
+  // face n+1/2 is stored at cell n; the bottom wall face of the channel (row -1)
+  // goes to its own array
+  T* out = fl;
+  long long idx = (long long)gx + (long long)gy * g.stride[1] + (long long)gz * g.stride[2];
+  long long cs = g.N;
+  if (CHAN && DIR == 1 && gy < 0) {
+    out = (T*)g.fwall;
+    idx = (long long)gx + (long long)gz * g.n[0];
+    cs = (long long)g.n[0] * g.n[2];
+  }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const int gk = gcomp_local<DIR>(k);
-    if (!STAGE2) fl[(long long)gk * g.N + idx] = T(0.25) * Fs[k];
-    fl[(long long)(5 + gk) * g.N + idx] = T(0.25) * dFs[k];
+    if (!STAGE2) out[(long long)gk * cs + idx] = T(0.25) * Fs[k];
+    out[(long long)(5 + gk) * cs + idx] = T(0.25) * dFs[k];
   }
 }
 
@@ -80,7 +108,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_FLUX_WAVES : HGKS_FLUX_
 flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop, int ntx,
                   int nty, int ntz, int nper) {
   if (*stop) return;
-  flux_fused_body<T, DIR, STAGE2, false>(g, q, fl, ntx, nty, ntz, nper);
+  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ntx, nty, ntz, nper);
 }
 
 template <typename T, int DIR>
@@ -88,14 +116,28 @@ __global__ void __launch_bounds__(256) flux_fused_varmu_kernel(Geo g, const doub
                                                                T* __restrict__ fl, const int* __restrict__ stop,
                                                                int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
-  flux_fused_body<T, DIR, false, true>(g, q, fl, ntx, nty, ntz, nper);
+  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ntx, nty, ntz, nper);
+}
+
+// Channel: walls in y, stretched y, mu(T) as given (one instantiation covers both
+// stages, the y-metric branches are uniform).
+template <typename T, int DIR, bool STAGE2>
+__global__ void __launch_bounds__(256) flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
+                                                              T* __restrict__ fl, const int* __restrict__ stop,
+                                                              int ntx, int nty, int ntz, int nper) {
+  if (*stop) return;
+  if (g.mu_exp != 0.0)
+    flux_fused_body<T, DIR, STAGE2, true, true>(g, q, fl, ntx, nty, ntz, nper);
+  else
+    flux_fused_body<T, DIR, STAGE2, false, true>(g, q, fl, ntx, nty, ntz, nper);
 }
 
 template <int DIR>
 void tile_grid(const Geo& g, int& ntx, int& nty, int& ntz, int& nper) {
   using TG = TileGeom<DIR>;
   ntx = (g.n[0] + TG::BX - 1) / TG::BX;
-  nty = (g.n[1] + TG::BY - 1) / TG::BY;
+  // with walls in y there are ny + 1 rows of y-faces (one tile row each)
+  nty = (g.n[1] + (DIR == 1 && g.wall_y ? 1 : 0) + TG::BY - 1) / TG::BY;
   ntz = (g.n[2] + TG::BZ - 1) / TG::BZ;
   nper = (ntx * nty * ntz + 7) / 8;
 }
@@ -107,7 +149,10 @@ template <typename T, int DIR, bool STAGE2, bool VAR_MU>
 static void launch_dir(const Geo& g, const double* q, T* fl, const int* stop, hipStream_t st) {
   int ntx, nty, ntz, nper;
   tile_grid<DIR>(g, ntx, nty, ntz, nper);
-  if (VAR_MU)
+  if (g.wall_y || g.stretch_y)
+    flux_fused_chan_kernel<T, DIR, STAGE2><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
+                                                                                          ntz, nper);
+  else if (VAR_MU)
     flux_fused_varmu_kernel<T, DIR><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty, ntz, nper);
   else
     flux_fused_kernel<T, DIR, STAGE2><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty, ntz, nper);

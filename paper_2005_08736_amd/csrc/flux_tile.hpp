@@ -63,27 +63,49 @@ __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz,
   }
 }
 
-// Cell averages along the normal of face-field entry e (six cells n-2 .. n+3,
-// periodic), as deviations from the reference state, in the local frame; the
-// global cell offsets of the six cells are returned in off.
-template <typename T, int DIR>
+// Cell averages along the normal of face-field entry e (six cells n-2 .. n+3),
+// as deviations from the reference state, in the local frame; the global cell
+// offsets of the six cells are returned in off.  Periodic axes wrap; with WALL,
+// y is not periodic and rows outside [0, ny) are wall ghosts (their offsets are
+// those of the mirror cells).
+template <typename T, int DIR, bool WALL = false>
 __device__ __forceinline__ void normal_stencil(const Geo& g, const double* __restrict__ q, int e, int x0, int y0,
                                                int z0, T (*v)[6], long long* off) {
   using TG = TileGeom<DIR>;
   const int ex = e % TG::FX, ey = (e / TG::FX) % TG::FY, ez = e / (TG::FX * TG::FY);
-  int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), wrapmod(y0 + ey - TG::HY, g.n[1]), wrapmod(z0 + ez - TG::HZ, g.n[2])};
-  const int nn = c[DIR], Nn = g.n[DIR];
-  const long long sn = g.stride[DIR];
-  const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
-                         (long long)nn * sn;
+  if (!WALL) {
+    int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), wrapmod(y0 + ey - TG::HY, g.n[1]),
+                wrapmod(z0 + ez - TG::HZ, g.n[2])};
+    const int nn = c[DIR], Nn = g.n[DIR];
+    const long long sn = g.stride[DIR];
+    const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
+                           (long long)nn * sn;
 #pragma unroll
-  for (int m = 0; m < 6; ++m) off[m] = base + (long long)wrapi(nn - 2 + m, Nn) * sn;
+    for (int m = 0; m < 6; ++m) off[m] = base + (long long)wrapi(nn - 2 + m, Nn) * sn;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const double* f = q + (long long)gcomp_local<DIR>(k) * g.N;
-    const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+    for (int k = 0; k < 5; ++k) {
+      const double* f = q + (long long)gcomp_local<DIR>(k) * g.N;
+      const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) v[k][m] = T(f[off[m]] - ref);
+      for (int m = 0; m < 6; ++m) v[k][m] = T(f[off[m]] - ref);
+    }
+  } else {
+    // x and z periodic, y unwrapped (ghost rows allowed)
+    int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), y0 + ey - TG::HY, wrapmod(z0 + ez - TG::HZ, g.n[2])};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[DIR] = DIR == 1 ? c[1] - 2 + m : wrapi(c[DIR] - 2 + m, g.n[DIR]);
+      double Q[5];
+      load_cell_wall(g, q, cc[0], cc[1], cc[2], Q);
+      int ym = cc[1] < 0 ? -1 - cc[1] : (cc[1] >= g.n[1] ? 2 * g.n[1] - 1 - cc[1] : cc[1]);
+      off[m] = (long long)cc[0] + (long long)ym * g.stride[1] + (long long)cc[2] * g.stride[2];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+        v[k][m] = T(Q[gcomp_local<DIR>(k)] - ref);
+      }
+    }
   }
 }
 
@@ -98,16 +120,18 @@ __host__ __device__ __forceinline__ void normal_recon(const T* v, T ih12, T& ql,
 }
 
 // Phase 1: face field (Q0 deviation and dQ0/dn, local frame) of the tile and its
-// tangential halo into ff[10][NFF].  The caller synchronizes.
-template <typename T, int DIR>
+// tangential halo into ff[10][NFF].  dn_scale is 1/h of the normal axis (for
+// y-faces of a stretched mesh, 1/(y' h) at the tile's face row).  The caller
+// synchronizes.
+template <typename T, int DIR, bool WALL = false>
 __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __restrict__ q, T* ff, int x0, int y0,
-                                                int z0) {
+                                                int z0, double dn_scale) {
   using TG = TileGeom<DIR>;
-  const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
+  const T ih12 = T(dn_scale * (1.0 / 12.0));
   for (int e = threadIdx.x; e < TG::NFF; e += 256) {
     T v[5][6];
     long long off[6];
-    normal_stencil<T, DIR>(g, q, e, x0, y0, z0, v, off);
+    normal_stencil<T, DIR, WALL>(g, q, e, x0, y0, z0, v, off);
     T Ql[5], Qr[5], Dn[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
@@ -124,9 +148,11 @@ __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __re
 // Phase 2 data: tangential fourth-order reconstruction, for the t1 Gauss point m
 // and both t2 Gauss points l, of Q0 (value, d/dt1, d/dt2) and of dQ0/dn (value)
 // from the 5 x 5 face neighbourhood whose corner sits at LDS index `corner`.
-// Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).
+// Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).  i1 is the
+// t1 metric factor at this Gauss point, i2m / i2p the t2 factors at l = 0 / 1.
 template <typename T, int DIR>
-__device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2, T (*Qg)[5], T (*Dg)[3][5]) {
+__device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2m, T i2p, T (*Qg)[5],
+                                        T (*Dg)[3][5]) {
   using TG = TileGeom<DIR>;
   constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
   constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
@@ -165,8 +191,8 @@ __device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T 
     Dg[1][0][k] = np;
     Dg[0][1][k] = d1m * i1;
     Dg[1][1][k] = d1p * i1;
-    Dg[0][2][k] = d2m * i2;
-    Dg[1][2][k] = d2p * i2;
+    Dg[0][2][k] = d2m * i2m;
+    Dg[1][2][k] = d2p * i2p;
   }
 }
 

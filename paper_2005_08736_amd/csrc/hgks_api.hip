@@ -45,10 +45,12 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, lam_star, total;
+  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, lam_star, ymet, fwall, total;
 };
 
-Layout layout_for(long long N, int precision) {
+Layout layout_for(const hgks_params* p) {
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  const size_t tf = p->precision == HGKS_PREC_F32FLUX ? sizeof(float) : sizeof(double);
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -59,13 +61,43 @@ Layout layout_for(long long N, int precision) {
   L.ctrl = take(sizeof(Ctrl));
   L.qs = take(sizeof(double) * 5 * N);
   L.rr = take(sizeof(double) * 5 * N);
-  L.fl = take((precision == HGKS_PREC_F32FLUX ? sizeof(float) : sizeof(double)) * 30 * N);
+  L.fl = take(tf * 30 * N);
   L.diag_part = take(sizeof(double) * diag_partial_doubles());
   L.diag_out = take(sizeof(double) * 64);
   L.speed_part = take(sizeof(double) * size_t((N + 255) / 256));
   L.lam_star = take(sizeof(double) * 5 * N);
+  // channel: metric tables of the stretched y mesh, fluxes of the bottom wall faces
+  L.ymet = take(p->stretch_b > 0.0 ? sizeof(double) * (size_t(kYmTableDoubles) * p->ny + 1) : 0);
+  L.fwall = take(p->bc_y == HGKS_BC_WALL_ISOTHERMAL ? tf * 10 * size_t(p->nx) * p->nz : 0);
   L.total = off;
   return L;
+}
+
+// Metric tables of the tanh mesh y = tanh(b (eta / (1.5 pi) - 1)) / tanh b on
+// eta in [0, 3 pi] (Sec. 3.3), in the layout the device reads (ym_* accessors).
+std::vector<double> metric_tables(int ny, double b) {
+  const double pi = 3.14159265358979323846;
+  const double deta = 3.0 * pi / ny;
+  const double gs = 1.0 / (2.0 * std::sqrt(3.0));
+  auto ymap = [&](double eta) { return std::tanh(b * (eta / (1.5 * pi) - 1.0)) / std::tanh(b); };
+  auto dymap = [&](double eta) {
+    double t = std::tanh(b * (eta / (1.5 * pi) - 1.0));
+    return b / (1.5 * pi) * (1.0 - t * t) / std::tanh(b);
+  };
+  std::vector<double> t(size_t(kYmTableDoubles) * ny + 1);
+  for (int j = 0; j < ny; ++j) {
+    const double dy = ymap((j + 1) * deta) - ymap(j * deta);
+    t[j] = 1.0 / dy;
+    t[ny + j] = dy;
+    for (int m = 0; m < 2; ++m) {
+      const double eta = (j + 0.5 + (m == 0 ? -gs : gs)) * deta;
+      const double d = dymap(eta);
+      t[3 * ny + 1 + 2 * j + m] = 1.0 / (d * deta);
+      t[5 * ny + 1 + 2 * j + m] = d * deta / dy;
+    }
+  }
+  for (int f = 0; f <= ny; ++f) t[2 * ny + f] = 1.0 / (dymap(f * deta) * deta);
+  return t;
 }
 
 int validate(const hgks_params* p) {
@@ -83,8 +115,12 @@ int validate(const hgks_params* p) {
   if (p->mode == HGKS_MODE_WENOZ) {
     if (!(p->weno_eps > 0.0) || p->weno_p < 1 || p->weno_p > 4 || !(p->c_art >= 0.0)) return HGKS_E_INVALID_ARG;
   }
-  // implemented so far: periodic boxes
-  if (p->bc_y != HGKS_BC_PERIODIC || p->stretch_b != 0.0 || p->body_force_x != 0.0) return HGKS_E_UNSUPPORTED;
+  if (!(p->stretch_b >= 0.0)) return HGKS_E_INVALID_ARG;
+  if (p->bc_y == HGKS_BC_WALL_ISOTHERMAL && !(p->T_wall > 0.0)) return HGKS_E_INVALID_ARG;
+  // the stretched mesh is the channel's wall-normal mesh; walls and stretching
+  // are implemented for the smooth mode
+  if (p->stretch_b > 0.0 && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_UNSUPPORTED;
+  if (p->mode == HGKS_MODE_WENOZ && (p->bc_y != HGKS_BC_PERIODIC || p->stretch_b > 0.0)) return HGKS_E_UNSUPPORTED;
   return HGKS_OK;
 }
 
@@ -98,7 +134,8 @@ Geo make_geo(const hgks_params* p) {
   g.stride[1] = p->nx;
   g.stride[2] = (long long)p->nx * p->ny;
   g.h[0] = p->lx / p->nx;
-  g.h[1] = p->ly / p->ny;
+  // stretched y: h[1] is the uniform spacing of eta on [0, 3 pi]
+  g.h[1] = p->stretch_b > 0.0 ? 3.0 * 3.14159265358979323846 / p->ny : p->ly / p->ny;
   g.h[2] = p->lz / p->nz;
   for (int a = 0; a < 3; ++a) g.inv_h[a] = 1.0 / g.h[a];
   g.gamma = p->gamma;
@@ -116,6 +153,12 @@ Geo make_geo(const hgks_params* p) {
   g.weno_eps = p->weno_eps;
   g.weno_p = p->weno_p;
   g.c_art = p->c_art;
+  g.wall_y = p->bc_y == HGKS_BC_WALL_ISOTHERMAL;
+  g.stretch_y = p->stretch_b > 0.0;
+  g.T_wall = p->T_wall;
+  g.fx = p->body_force_x;
+  g.ym = nullptr;
+  g.fwall = nullptr;
   g.rho_ref = 1.0;
   g.p_ref = 1.0;
   g.E_ref = g.p_ref * g.inv_gm1;
@@ -202,11 +245,11 @@ void stage1(hgks_handle* h, const double* cur, double* other, int step) {
     launch_stage1(h->geo, cur, fl_dir<double>(h, 0), other, h->rr, h->ctrl, step, h->stream);
 }
 
-void stage2(hgks_handle* h, double* other, int step) {
+void stage2(hgks_handle* h, const double* cur, double* other, int step) {
   if (f32(h))
-    launch_stage2(h->geo, h->rr, fl_dir<float>(h, 0), other, h->ctrl, h->speed_part, step, h->stream);
+    launch_stage2(h->geo, h->rr, fl_dir<float>(h, 0), cur, other, h->ctrl, h->speed_part, step, h->stream);
   else
-    launch_stage2(h->geo, h->rr, fl_dir<double>(h, 0), other, h->ctrl, h->speed_part, step, h->stream);
+    launch_stage2(h->geo, h->rr, fl_dir<double>(h, 0), cur, other, h->ctrl, h->speed_part, step, h->stream);
 }
 
 }  // namespace
@@ -216,7 +259,7 @@ extern "C" {
 size_t hgks_workspace_bytes(const hgks_params* p) {
   int v = validate(p);
   if (v != HGKS_OK) return 0;
-  return layout_for((long long)p->nx * p->ny * p->nz, p->precision).total;
+  return layout_for(p).total;
 }
 
 int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes, void* hip_stream,
@@ -227,7 +270,7 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   if (v != HGKS_OK) return v;
   if (!q) return HGKS_E_INVALID_ARG;
   const long long N = (long long)p->nx * p->ny * p->nz;
-  Layout L = layout_for(N, p->precision);
+  Layout L = layout_for(p);
   if (!workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return HGKS_E_WORKSPACE;
   hgks_handle* h = new (std::nothrow) hgks_handle;
@@ -246,11 +289,22 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   h->diag_out = reinterpret_cast<double*>(h->ws + L.diag_out);
   h->speed_part = reinterpret_cast<double*>(h->ws + L.speed_part);
   h->lam_star = reinterpret_cast<double*>(h->ws + L.lam_star);
+  if (h->geo.stretch_y) h->geo.ym = reinterpret_cast<const double*>(h->ws + L.ymet);
+  if (h->geo.wall_y) h->geo.fwall = h->ws + L.fwall;
   h->steps_done = 0;
   h->failed_step = -1;
   h->profiling = false;
   for (int k = 0; k < HGKS_KCLASS_COUNT; ++k) { h->prof_ms[k] = 0.0; h->prof_count[k] = 0; }
   launch_reset_ctrl(h->ctrl, h->stream);
+  std::vector<double> tables;  // kept alive until the stream synchronization below
+  if (h->geo.stretch_y) {
+    tables = metric_tables(p->ny, p->stretch_b);
+    if (hipMemcpyAsync(h->ws + L.ymet, tables.data(), sizeof(double) * tables.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess) {
+      delete h;
+      return HGKS_E_DEVICE;
+    }
+  }
   double c0[5];
   for (int k = 0; k < 5; ++k) {
     if (hipMemcpyAsync(&c0[k], q + (size_t)k * N, sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess) {
@@ -297,7 +351,7 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
       prof_end(h, on);
       all_fluxes(h, other, true, &h->ctrl->flag);
       on = prof_begin(h, HGKS_KCLASS_STAGE2);
-      stage2(h, other, step);
+      stage2(h, cur, other, step);
       prof_end(h, on);
       double* t = cur;
       cur = other;
@@ -370,7 +424,8 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n) {
   if (!h || !q_n || !lam_np1 || !lam_n || !(dt > 0.0)) return HGKS_E_INVALID_ARG;
   if (lam_n == lam_np1 || lam_n == q_n) return HGKS_E_INVALID_ARG;
-  if (h->p.precision != HGKS_PREC_F64 || h->p.mu_exp != 0.0 || h->p.mode != HGKS_MODE_SMOOTH)
+  if (h->p.precision != HGKS_PREC_F64 || h->p.mu_exp != 0.0 || h->p.mode != HGKS_MODE_SMOOTH || h->geo.wall_y ||
+      h->geo.stretch_y || h->geo.fx != 0.0)
     return HGKS_E_UNSUPPORTED;
   const Geo& g = h->geo;
   hipStream_t st = h->stream;

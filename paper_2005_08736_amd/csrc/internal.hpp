@@ -10,8 +10,8 @@ template <typename TF>
 void launch_stage1(const Geo& g, const double* qn, const TF* fl, double* qs, double* rr, Ctrl* ctrl, int step,
                    hipStream_t st);
 template <typename TF>
-void launch_stage2(const Geo& g, const double* rr, const TF* fl, double* qout, Ctrl* ctrl, double* part, int step,
-                   hipStream_t st);
+void launch_stage2(const Geo& g, const double* rr, const TF* fl, const double* qn, double* qout, Ctrl* ctrl,
+                   double* part, int step, hipStream_t st);
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st);
 size_t speed_partials(const Geo& g);
 void launch_reset_ctrl(Ctrl* ctrl, hipStream_t st);

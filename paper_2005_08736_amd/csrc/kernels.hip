@@ -17,17 +17,41 @@ __device__ __forceinline__ void cell_coords(const Geo& g, long long idx, int* c)
 // ---------------------------------------------------------------------------
 // Stage updates.
 // ---------------------------------------------------------------------------
-// max over axes of (|U_d| + c)/h_d, and whether the state is physical
-__device__ __forceinline__ double cell_speed(const Geo& g, const double* Q, bool& ok) {
+// 1/width of row j along y (the row height on a stretched mesh)
+__device__ __forceinline__ double inv_width_y(const Geo& g, int j) {
+  return g.stretch_y ? ym_inv_dy(g, j) : g.inv_h[1];
+}
+
+// max over axes of (|U_d| + c)/dx_d of a cell in row j, and whether the state is physical
+__device__ __forceinline__ double cell_speed(const Geo& g, const double* Q, int j, bool& ok) {
   double ir = 1.0 / Q[0];
   double U = Q[1] * ir, V = Q[2] * ir, W = Q[3] * ir;
   double p = g.gm1 * (Q[4] - 0.5 * Q[0] * (U * U + V * V + W * W));
   ok = (Q[0] > 0.0) && (p > 0.0) && isfinite(p) && isfinite(Q[0]);
   double c = sqrt(g.gamma * p * ir);
   double s = (fabs(U) + c) * g.inv_h[0];
-  s = fmax(s, (fabs(V) + c) * g.inv_h[1]);
+  s = fmax(s, (fabs(V) + c) * inv_width_y(g, j));
   s = fmax(s, (fabs(W) + c) * g.inv_h[2]);
   return s;
+}
+
+// face below cell c along direction d: its array and index (the bottom wall face
+// of the channel lives in its own array, component stride nx nz)
+template <typename TF>
+__device__ __forceinline__ const TF* lower_face(const Geo& g, const TF* F, long long idx, const int* c, int d,
+                                                long long& lo, long long& cs) {
+  cs = g.N;
+  if (c[d] > 0) {
+    lo = idx - g.stride[d];
+    return F;
+  }
+  if (d == 1 && g.wall_y) {
+    lo = (long long)c[0] + (long long)c[2] * g.n[0];
+    cs = (long long)g.n[0] * g.n[2];
+    return static_cast<const TF*>(g.fwall);
+  }
+  lo = idx + (long long)(g.n[d] - 1) * g.stride[d];
+  return F;
 }
 
 // block maximum of v (256 threads) written to part[blockIdx.x]
@@ -47,9 +71,11 @@ __device__ __forceinline__ void divergence(const Geo& g, const double* fl, long 
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double* F = fl + (long long)d * 10 * g.N;
-    long long lo = c[d] == 0 ? idx + (long long)(g.n[d] - 1) * g.stride[d] : idx - g.stride[d];
-    if (L) l -= (F[(long long)k * g.N + idx] - F[(long long)k * g.N + lo]) * g.inv_h[d];
-    dl -= (F[(long long)(5 + k) * g.N + idx] - F[(long long)(5 + k) * g.N + lo]) * g.inv_h[d];
+    long long lo, cs;
+    const double* Fl = lower_face(g, F, idx, c, d, lo, cs);
+    const double ih = d == 1 ? inv_width_y(g, c[1]) : g.inv_h[d];
+    if (L) l -= (F[(long long)k * g.N + idx] - Fl[(long long)k * cs + lo]) * ih;
+    dl -= (F[(long long)(5 + k) * g.N + idx] - Fl[(long long)(5 + k) * cs + lo]) * ih;
   }
   if (L) *L = l;
   *dL = dl;
@@ -97,10 +123,11 @@ __device__ __forceinline__ void divergence(const Geo& g, const float* fl, long l
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const float* F = fl + (long long)d * 10 * g.N;
-    long long lo = c[d] == 0 ? idx + (long long)(g.n[d] - 1) * g.stride[d] : idx - g.stride[d];
-    const float ih = float(g.inv_h[d]);
-    if (L) add_neg_scaled_diff(l, F[(long long)k * g.N + idx], F[(long long)k * g.N + lo], ih);
-    add_neg_scaled_diff(dl, F[(long long)(5 + k) * g.N + idx], F[(long long)(5 + k) * g.N + lo], ih);
+    long long lo, cs;
+    const float* Fl = lower_face(g, F, idx, c, d, lo, cs);
+    const float ih = float(d == 1 ? inv_width_y(g, c[1]) : g.inv_h[d]);
+    if (L) add_neg_scaled_diff(l, F[(long long)k * g.N + idx], Fl[(long long)k * cs + lo], ih);
+    add_neg_scaled_diff(dl, F[(long long)(5 + k) * g.N + idx], Fl[(long long)(5 + k) * cs + lo], ih);
   }
   if (L) *L = l.value();
   *dL = dl.value();
@@ -148,18 +175,22 @@ __global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __rest
     rr[(long long)k * g.N + idx] = q0 + dt * L + (dt * dt / 6.0) * dL;
   }
   bool ok;
-  (void)cell_speed(g, Qs, ok);
+  (void)cell_speed(g, Qs, c[1], ok);
   if (!ok) {
     ctrl->fail_step = step;
     ctrl->flag = 1;
   }
 }
 
-// Q^{n+1} = R + dt^2/3 dL(Q*); block maxima of the next step's CFL speed.
+// Q^{n+1} = R + dt^2/3 dL(Q*); then the channel's constant body force f_x
+// (Sec. 3.3), with the trapezoidal rule over the step:
+//   (rho U)^{n+1} += dt/2 (rho^{n+1} + rho^n) f_x,
+//   (rho E)^{n+1} += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x;
+// block maxima of the next step's CFL speed.
 template <typename TF>
 __global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __restrict__ rr, const TF* __restrict__ fl,
-                                                     double* __restrict__ qout, Ctrl* ctrl, double* __restrict__ part,
-                                                     int step) {
+                                                     const double* __restrict__ qn, double* __restrict__ qout,
+                                                     Ctrl* ctrl, double* __restrict__ part, int step) {
   if (ctrl->flag) return;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const double dt = ctrl->dt;
@@ -173,10 +204,16 @@ __global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __rest
       double dL;
       divergence(g, fl, idx, c, k, nullptr, &dL);
       Qn[k] = rr[(long long)k * g.N + idx] + (dt * dt / 3.0) * dL;
-      qout[(long long)k * g.N + idx] = Qn[k];
     }
+    if (g.fx != 0.0) {
+      const double mx_old = qn[g.N + idx];
+      Qn[1] = Qn[1] + 0.5 * dt * (Qn[0] + qn[idx]) * g.fx;
+      Qn[4] = Qn[4] + 0.5 * dt * (Qn[1] + mx_old) * g.fx;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qout[(long long)k * g.N + idx] = Qn[k];
     bool ok;
-    speed = cell_speed(g, Qn, ok);
+    speed = cell_speed(g, Qn, c[1], ok);
     if (!ok) {
       ctrl->fail_step = step;
       ctrl->flag = 1;
@@ -194,8 +231,10 @@ __global__ void __launch_bounds__(256) check_state_kernel(Geo g, const double* _
     double Q[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];
+    int c[3];
+    cell_coords<0>(g, idx, c);
     bool ok;
-    speed = cell_speed(g, Q, ok);
+    speed = cell_speed(g, Q, c[1], ok);
     if (!ok) {
       ctrl->fail_step = step;
       ctrl->flag = 1;
@@ -230,15 +269,23 @@ __global__ void __launch_bounds__(256) operator_kernel(Geo g, const TF* __restri
 }
 
 // Face fluxes of one direction as FP64 face averages with the constant reference
-// pressure restored in the normal-momentum component (parity entry point).
+// pressure restored in the normal-momentum component (parity entry point).  On a
+// stretched y the Gauss points of x- and z-faces carry their shares of the row
+// height, so the constant comes back with the same weights.
 template <typename TF>
 __global__ void __launch_bounds__(256) export_flux_kernel(Geo g, int dir, const TF* __restrict__ fl,
                                                           double* __restrict__ F, double* __restrict__ dF) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.N) return;
+  double pref = g.p_ref;
+  if (g.stretch_y && dir != 1) {
+    int c[3];
+    cell_coords<0>(g, idx, c);
+    pref = g.p_ref * (0.5 * (ym_gp_w(g, c[1], 0) + ym_gp_w(g, c[1], 1)));
+  }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    F[(long long)k * g.N + idx] = double(fl[(long long)k * g.N + idx]) + (k == 1 + dir ? g.p_ref : 0.0);
+    F[(long long)k * g.N + idx] = double(fl[(long long)k * g.N + idx]) + (k == 1 + dir ? pref : 0.0);
     dF[(long long)k * g.N + idx] = double(fl[(long long)(5 + k) * g.N + idx]);
   }
 }
@@ -267,12 +314,14 @@ template void launch_stage1<double>(const Geo&, const double*, const double*, do
 template void launch_stage1<float>(const Geo&, const double*, const float*, double*, double*, Ctrl*, int, hipStream_t);
 
 template <typename TF>
-void launch_stage2(const Geo& g, const double* rr, const TF* fl, double* qout, Ctrl* ctrl, double* part, int step,
-                   hipStream_t st) {
-  stage2_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qout, ctrl, part, step);
+void launch_stage2(const Geo& g, const double* rr, const TF* fl, const double* qn, double* qout, Ctrl* ctrl,
+                   double* part, int step, hipStream_t st) {
+  stage2_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qn, qout, ctrl, part, step);
 }
-template void launch_stage2<double>(const Geo&, const double*, const double*, double*, Ctrl*, double*, int, hipStream_t);
-template void launch_stage2<float>(const Geo&, const double*, const float*, double*, Ctrl*, double*, int, hipStream_t);
+template void launch_stage2<double>(const Geo&, const double*, const double*, const double*, double*, Ctrl*, double*,
+                                    int, hipStream_t);
+template void launch_stage2<float>(const Geo&, const double*, const float*, const double*, double*, Ctrl*, double*,
+                                   int, hipStream_t);
 
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st) {
   check_state_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, q, ctrl, part, step);

@@ -1,0 +1,201 @@
+"""GPU parity of the channel set-up (Sec. 3.3: isothermal no-slip walls in y,
+tanh-stretched wall-normal mesh, constant streamwise body force) against the
+FP64 oracle: face fluxes, the operator, stepping, a uniform-mesh wall case, the
+rest state, diagnostics, the 128^3 workload at sampled cells, and the FP32-flux
+form against the FP64 path."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_08736_amd import cases, hgks
+from tests.test_gpu_parity import rel_l2_fields
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    return torch.device("cuda:0")
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(q):
+    return torch.from_numpy(np.ascontiguousarray(q)).to(dev())
+
+
+def uniform_wall_case(nx, ny, nz, seed=0):
+    """Walls at y = -1, 1 on a uniform mesh; Poiseuille profile with 10% noise."""
+    p = cases.channel_params(nx, ny, nz, stretch_b=0.0, ly=2.0)
+    rng = np.random.default_rng(seed)
+    y = -1.0 + (np.arange(ny) + 0.5) * 2.0 / ny
+    U = 1.5 * (1 - y ** 2)[None, :, None] * (1 + 0.1 * rng.uniform(-1, 1, size=(nz, ny, nx)))
+    V = 0.02 * rng.uniform(-1, 1, size=(nz, ny, nx))
+    q = np.empty((5, nz, ny, nx))
+    q[0] = 1.0
+    q[1] = U
+    q[2] = V
+    q[3] = 0.0
+    q[4] = p["T_wall"] / (p["gamma"] - 1) + 0.5 * (U ** 2 + V ** 2)
+    return p, q
+
+
+def stretched_case(nx, ny, nz, seed=0):
+    p = cases.channel_params(nx, ny, nz)
+    return p, cases.channel_state(p, seed=seed)
+
+
+CASES = {
+    "chan32x32x16": lambda: stretched_case(32, 32, 16, seed=0),
+    "chan13x10x7": lambda: stretched_case(13, 10, 7, seed=1),
+    "wall_uniform16x12x8": lambda: uniform_wall_case(16, 12, 8, seed=2),
+}
+
+
+def face_areas(p, direction):
+    """Area of the faces of each row j (broadcast over [nz][ny][nx])."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    hx, hz = p["lx"] / nx, p["lz"] / nz
+    if p["stretch_b"] > 0:
+        yf, _ = cases.channel_y(ny, p["stretch_b"])
+        dy = np.diff(yf)
+    else:
+        dy = np.full(ny, p["ly"] / ny)
+    area = {0: hz * dy, 1: np.full(ny, hx * hz), 2: hx * dy}[direction]
+    return area[None, :, None]
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_channel_face_flux_matches_oracle(case, direction):
+    announce(f"channel face_flux {case} dir={direction}")
+    p, q = CASES[case]()
+    s = hgks.Solver(p, to_dev(q))
+    F, dF = s.face_flux(direction)
+    torch.cuda.synchronize()
+    Fr, dFr = oracle.face_flux(p, q, direction)
+    area = face_areas(p, direction)
+    Fr, dFr = Fr / area, dFr / area
+    F, dF = F.cpu().numpy(), dF.cpu().numpy()
+    # T_w ~ 71: the same thermal cancellations as the Taylor-Green case
+    scF, scD = np.abs(Fr).max(), np.abs(dFr).max()
+    for k in range(5):
+        assert np.abs(F[k] - Fr[k]).max() <= 1e-13 * scF, (k, np.abs(F[k] - Fr[k]).max(), scF)
+        assert np.abs(dF[k] - dFr[k]).max() <= 1e-11 * scD, (k, np.abs(dF[k] - dFr[k]).max(), scD)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_channel_operator_matches_oracle(case):
+    announce(f"channel operator {case}")
+    p, q = CASES[case]()
+    s = hgks.Solver(p, to_dev(q))
+    L, dL = s.operator()
+    torch.cuda.synchronize()
+    Lr, dLr = oracle.operator(p, q)
+    # rounding scale: face fluxes over the smallest cell width
+    ny = p["ny"]
+    dy = np.diff(cases.channel_y(ny, p["stretch_b"])[0]) if p["stretch_b"] > 0 else np.full(ny, p["ly"] / ny)
+    hmin = min(p["lx"] / p["nx"], p["lz"] / p["nz"], float(dy.min()))
+    for A, Ar, tol, d in ((L.cpu().numpy(), Lr, 1e-13, 0), (dL.cpu().numpy(), dLr, 1e-11, 1)):
+        for k in range(5):
+            sc = max(np.abs(oracle.face_flux(p, q, a)[d][k] / face_areas(p, a)).max() for a in range(3)) / hmin
+            assert np.abs(A[k] - Ar[k]).max() <= tol * sc, (k, np.abs(A[k] - Ar[k]).max(), sc)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_channel_steps_match_oracle_every_step(case):
+    p, q = CASES[case]()
+    steps = 6
+    announce(f"channel {case}, {steps} CFL steps")
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    qr = q.copy()
+    for i in range(steps):
+        dts = s.step(1, return_dt=True)
+        qr, dtr = oracle.step(p, qr, 1)
+        assert abs(dts[0] - dtr[0]) <= 1e-14 * dtr[0], (i, dts[0], dtr[0])
+        errs = rel_l2_fields(qd.cpu().numpy(), qr)
+        assert max(errs) <= 1e-12, (i, errs)
+    announce(f"  after {steps} steps: max rel L2 {max(errs):.2e}")
+
+
+def test_channel_rest_state_bitwise():
+    announce("channel rest state")
+    p = cases.channel_params(16, 12, 8, body_force_x=0.0)
+    q = cases.uniform_state(16, 12, 8, rho=1.0, vel=(0.0, 0.0, 0.0), p=p["T_wall"])
+    qd = to_dev(q)
+    hgks.Solver(p, qd).step(3)
+    assert np.array_equal(qd.cpu().numpy(), q)
+
+
+def test_channel_diagnostics_match_oracle():
+    for case in ("chan32x32x16", "wall_uniform16x12x8"):
+        announce(f"channel diagnostics {case}")
+        p, q = CASES[case]()
+        qd = to_dev(q)
+        s = hgks.Solver(p, qd)
+        s.step(2)
+        d = s.diagnostics()
+        dr = oracle.diagnostics(p, qd.cpu().numpy())
+        for name in hgks.DIAG_NAMES:
+            a, b = d[name], dr[name]
+            scale = {"mom_y": dr["mom_x"], "mom_z": dr["mom_x"], "eps2": dr["eps1"], "eps3": dr["eps1"],
+                     "p_theta": dr["eps1"] * 1e3, "S_u": 1.0, "dudx3": dr["dudx2"], "dvdy3": dr["dvdy2"],
+                     "dwdz3": dr["dwdz2"], "dudx4": dr["dudx4"] + 1e-300}.get(name, abs(b))
+            assert abs(a - b) <= 1e-12 * max(abs(scale), 1e-300) + 1e-300, (case, name, a, b)
+
+
+def test_channel_fp32_form_against_fp64_path():
+    n, steps = 32, 20
+    announce(f"channel FP32 form vs FP64, {n}^3, {steps} steps")
+    p = cases.channel_params(n, n, n)
+    q = cases.channel_state(p, seed=3)
+    a = to_dev(q)
+    dts = hgks.Solver(p, a).step(steps, return_dt=True)
+    p32 = dict(p)
+    p32["precision"] = hgks.PREC_F32FLUX
+    b = to_dev(q)
+    s32 = hgks.Solver(p32, b)
+    for dt in dts:
+        s32.step(1, dt=dt)
+    errs = rel_l2_fields(b.cpu().numpy(), a.cpu().numpy())
+    announce(f"  FP32 form rel L2 per field {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-5, errs
+
+
+def test_channel128_full_size_sampled_step():
+    """One CFL step of the 128^3 channel (the benchmarked channel workload) in the
+    kernels and launch shapes of the full-size run; the oracle checks dt on the
+    whole box and Q^{n+1} at sampled cells from windows 13 cells wide in x and z
+    spanning the whole wall-normal extent (walls and mesh are those of the box)."""
+    n = 128
+    announce("channel 128^3 sampled step")
+    p = cases.channel_params(n, n, n)
+    q = cases.channel_state(p, seed=0)
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    dts = s.step(1, return_dt=True)
+    dt_ref = oracle.cfl_dt(p, q)
+    assert abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
+    q1 = qd.cpu().numpy()
+    rng = np.random.default_rng(128)
+    pts = [tuple(rng.integers(0, n, size=3)) for _ in range(4)] + [(0, 0, 0), (5, n - 1, 9), (n - 1, 1, n - 1)]
+    hx, hz = p["lx"] / n, p["lz"] / n
+    for c in pts:
+        ii = np.arange(c[0] - 6, c[0] + 7) % n
+        kk = np.arange(c[2] - 6, c[2] + 7) % n
+        win = np.ascontiguousarray(q[:, kk][:, :, :, ii])
+        pw = dict(p)
+        pw.update(nx=13, nz=13, lx=13 * hx, lz=13 * hz)
+        qw, _ = oracle.step(pw, win, 1, dt=dts[0])
+        got = q1[:, c[2], c[1], c[0]]
+        ref = qw[:, 6, c[1], 6]
+        assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(np.abs(ref), 1.0)), (c, got - ref)
