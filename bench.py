@@ -117,6 +117,55 @@ def adjoint_timing(r, reps, torch):
     return out
 
 
+def other_workloads(args, torch, np, cases, hgks, dev):
+    """Throughput of the paper's other two workloads, each in its own solver:
+    decaying isotropic turbulence at 256^3 (WENO-Z + full flux, mu ~ T^0.76,
+    Ma_t = 0.5, seed 0) in FP64 and the FP32-flux form, and the turbulent
+    channel at 128^3 (walls, tanh mesh, body force; FP64)."""
+    out = {}
+
+    def timed(name, p, q0, steps):
+        q = torch.from_numpy(q0).to(dev)
+        s = hgks.Solver(p, q)
+        s.step(2)
+        s.profile(True)
+        s.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dts = s.step(steps, return_dt=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = s.profile_read()
+        s.profile(False)
+        ms1, c1 = prof["flux_stage1"]
+        n = p["nx"] * p["ny"] * p["nz"]
+        r = {"value": n * steps / el / 1e6, "unit": UNIT, "ms_per_step": el / steps * 1e3, "steps": steps,
+             "cells": n, "dt": dts[0], "flux_stage1_avg_launch_ms": ms1 / max(c1, 1)}
+        log(f"[bench] {name}: {r['ms_per_step']:.2f} ms/step, {r['value']:.1f} Mcell-updates/s")
+        s.close()
+        return r, q
+
+    log("[bench] building isotropic 256^3 initial state (Ma_t 0.5, seed 0)")
+    qi = cases.isotropic_state(256, 0, 0.5)
+    pi = dict(cases.isotropic_params(256, 0.5))
+    r64, a = timed("isotropic 256^3 mode Z FP64", pi, qi, args.other_steps)
+    pi32 = dict(pi)
+    pi32["precision"] = hgks.PREC_F32FLUX
+    r32, b = timed("isotropic 256^3 mode Z FP32 form", pi32, qi, args.other_steps)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    mom = float(np.sqrt(np.sum(a[1:4] ** 2)))
+    rel = max(float(np.linalg.norm(b[k] - a[k])) / (mom if 1 <= k <= 3 else float(np.linalg.norm(a[k])))
+              for k in range(5))
+    r32["rel_l2_vs_fp64_after_steps"] = rel
+    r32["note"] = "each form takes its own CFL steps; the states are compared after the same number of steps"
+    out["isotropic_256_modez_fp64"] = r64
+    out["isotropic_256_modez_fp32"] = r32
+    pc = dict(cases.channel_params(128, 128, 128))
+    rc, _ = timed("channel 128^3 FP64", pc, cases.channel_state(pc, seed=0), 4 * args.other_steps)
+    out["channel_128_fp64"] = rc
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +175,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--adjoint-reps", type=int, default=5)
+    ap.add_argument("--other-steps", type=int, default=5,
+                    help="timed steps of the isotropic (mode Z) and channel workloads (0: skip them)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -174,6 +225,7 @@ def main():
     r64 = run(hgks.PREC_F64)
     adj = adjoint_timing(r64, args.adjoint_reps, torch)
     r32 = run(hgks.PREC_F32FLUX)
+    others = other_workloads(args, torch, np, cases, hgks, dev) if args.other_steps > 0 else None
     value = r64["value"]
     ms_per_step = r64["ms"]
     dts = r64["dts"]
@@ -228,6 +280,7 @@ def main():
         "roofline": roofline,
         "fp32_form": fp32,
         "adjoint": adj,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

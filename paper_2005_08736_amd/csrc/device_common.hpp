@@ -80,20 +80,23 @@ __host__ __device__ __forceinline__ void wall_ghost(const Geo& g, double* Q) {
   Q[4] = p / g.gm1 + 0.5 * rg * (U * U + V * V + W * W);
 }
 
-// The conservative variables of cell (x, y, z), global frame; with walls in y a
-// row outside [0, ny) is the ghost of its mirror row (-1 - y below, 2 ny - 1 - y
-// above).  x and z are in range.
+// Row of the cell that supplies row y when walls bound y: rows outside [0, ny)
+// are ghosts of their mirror rows (-1 - y below, 2 ny - 1 - y above).  Rows more
+// than three beyond a wall only feed faces outside the grid, whose results are
+// discarded; they are clamped into the grid so that every read stays in bounds.
+__host__ __device__ __forceinline__ int wall_row(const Geo& g, int y, bool& ghost) {
+  ghost = y < 0 || y >= g.n[1];
+  int ym = y < 0 ? -1 - y : (y >= g.n[1] ? 2 * g.n[1] - 1 - y : y);
+  ym = ym < 0 ? 0 : (ym >= g.n[1] ? g.n[1] - 1 : ym);
+  return ym;
+}
+
+// The conservative variables of cell (x, y, z), global frame, with walls in y
+// (see wall_row); x and z are in range.
 __host__ __device__ __forceinline__ void load_cell_wall(const Geo& g, const double* q, int x, int y, int z,
                                                         double* Q) {
-  int ym = y;
-  bool ghost = false;
-  if (y < 0) {
-    ym = -1 - y;
-    ghost = true;
-  } else if (y >= g.n[1]) {
-    ym = 2 * g.n[1] - 1 - y;
-    ghost = true;
-  }
+  bool ghost;
+  const int ym = wall_row(g, y, ghost);
   const long long idx = (long long)x + (long long)ym * g.stride[1] + (long long)z * g.stride[2];
 #pragma unroll
   for (int k = 0; k < 5; ++k) Q[k] = q[(long long)k * g.N + idx];

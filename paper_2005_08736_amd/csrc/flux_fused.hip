@@ -21,9 +21,8 @@ namespace hgks {
 
 template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN>
 __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
-                                                int ntx, int nty, int ntz, int nper) {
+                                                T* ff, int ntx, int nty, int ntz, int nper) {
   using TG = TileGeom<DIR>;
-  __shared__ T ff[10 * TG::NFF];
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
@@ -108,7 +107,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_FLUX_WAVES : HGKS_FLUX_
 flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop, int ntx,
                   int nty, int ntz, int nper) {
   if (*stop) return;
-  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ntx, nty, ntz, nper);
+  __shared__ T ff[10 * TileGeom<DIR>::NFF];
+  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ff, ntx, nty, ntz, nper);
 }
 
 template <typename T, int DIR>
@@ -116,20 +116,21 @@ __global__ void __launch_bounds__(256) flux_fused_varmu_kernel(Geo g, const doub
                                                                T* __restrict__ fl, const int* __restrict__ stop,
                                                                int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
-  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ntx, nty, ntz, nper);
+  __shared__ T ff[10 * TileGeom<DIR>::NFF];
+  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ff, ntx, nty, ntz, nper);
 }
 
-// Channel: walls in y, stretched y, mu(T) as given (one instantiation covers both
-// stages, the y-metric branches are uniform).
-template <typename T, int DIR, bool STAGE2>
-__global__ void __launch_bounds__(256) flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
+// Channel: walls in y and/or the stretched y mesh (the metric branches are
+// uniform over the launch).
+template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(VAR_MU ? 1 : (sizeof(T) == 8 ? HGKS_FLUX_WAVES : HGKS_FLUX_WAVES_F32))))
+flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
                                                               T* __restrict__ fl, const int* __restrict__ stop,
                                                               int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
-  if (g.mu_exp != 0.0)
-    flux_fused_body<T, DIR, STAGE2, true, true>(g, q, fl, ntx, nty, ntz, nper);
-  else
-    flux_fused_body<T, DIR, STAGE2, false, true>(g, q, fl, ntx, nty, ntz, nper);
+  __shared__ T ff[10 * TileGeom<DIR>::NFF];
+  flux_fused_body<T, DIR, STAGE2, VAR_MU, true>(g, q, fl, ff, ntx, nty, ntz, nper);
 }
 
 template <int DIR>
@@ -150,8 +151,8 @@ static void launch_dir(const Geo& g, const double* q, T* fl, const int* stop, hi
   int ntx, nty, ntz, nper;
   tile_grid<DIR>(g, ntx, nty, ntz, nper);
   if (g.wall_y || g.stretch_y)
-    flux_fused_chan_kernel<T, DIR, STAGE2><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
-                                                                                          ntz, nper);
+    flux_fused_chan_kernel<T, DIR, STAGE2, VAR_MU><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx,
+                                                                                                  nty, ntz, nper);
   else if (VAR_MU)
     flux_fused_varmu_kernel<T, DIR><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty, ntz, nper);
   else
