@@ -153,57 +153,6 @@ __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __re
   }
 }
 
-// Phase 2 data: tangential fourth-order reconstruction, for the t1 Gauss point m
-// and both t2 Gauss points l, of Q0 (value, d/dt1, d/dt2) and of dQ0/dn (value)
-// from the 5 x 5 face neighbourhood whose corner sits at LDS index `corner`.
-// Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).  i1 is the
-// t1 metric factor at this Gauss point, i2m / i2p the t2 factors at l = 0 / 1.
-template <typename T, int DIR>
-__device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2m, T i2p, T (*Qg)[5],
-                                        T (*Dg)[3][5]) {
-  using TG = TileGeom<DIR>;
-  constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
-  constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    // keep the scheduler from hoisting the next component's LDS reads: it would
-    // otherwise hold all 250 values at once and drop the occupancy to one wave
-    asm volatile("" ::: "memory");
-    const T* f0 = ff + k * TG::NFF + corner;
-    const T* fn = ff + (5 + k) * TG::NFF + corner;
-    T rv[5], rd[5], rn[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-      T line[5], lined[5];
-#pragma unroll
-      for (int a = 0; a < 5; ++a) {
-        line[a] = f0[a * s1 + r * s2];
-        lined[a] = fn[a * s1 + r * s2];
-      }
-      T vm, vp, dm, dp, nm, np;
-      tang_val(line, vm, vp);
-      tang_der(line, dm, dp);
-      tang_val(lined, nm, np);
-      rv[r] = m ? vp : vm;
-      rd[r] = m ? dp : dm;
-      rn[r] = m ? np : nm;
-    }
-    T vm, vp, d2m, d2p, d1m, d1p, nm, np;
-    tang_val(rv, vm, vp);
-    tang_der(rv, d2m, d2p);
-    tang_val(rd, d1m, d1p);
-    tang_val(rn, nm, np);
-    Qg[0][k] = vm;
-    Qg[1][k] = vp;
-    Dg[0][0][k] = nm;
-    Dg[1][0][k] = np;
-    Dg[0][1][k] = d1m * i1;
-    Dg[1][1][k] = d1p * i1;
-    Dg[0][2][k] = d2m * i2m;
-    Dg[1][2][k] = d2p * i2p;
-  }
-}
-
 // Explicit tangential weights at Gauss point m (0: -, 1: +) for value and
 // derivative, cell order j-2 .. j+2 (the even/odd forms of tang_val/tang_der).
 template <typename T>
@@ -219,6 +168,78 @@ __host__ __device__ __forceinline__ void tang_weights(int m, T* wv, T* wd) {
   wd[2] = s * T(kDs0);
   wd[3] = s * T(kDs1) + T(kDa1);
   wd[4] = s * T(kDs2) + T(kDa2);
+}
+
+// The same weights as tables, [m][value 0..4, derivative 0..4].
+#define HGKS_TANG_ROW(sg)                                                                                        \
+  {kVe2 - (sg) * kVo2, kVe1 - (sg) * kVo1, kVe0, kVe1 + (sg) * kVo1, kVe2 + (sg) * kVo2, (sg) * kDs2 - kDa2,      \
+   (sg) * kDs1 - kDa1, (sg) * kDs0, (sg) * kDs1 + kDa1, (sg) * kDs2 + kDa2}
+static __constant__ double kTangW64[2][10] = {HGKS_TANG_ROW(-1.0), HGKS_TANG_ROW(1.0)};
+static __constant__ float kTangW32[2][10] = {HGKS_TANG_ROW(-1.0), HGKS_TANG_ROW(1.0)};
+#undef HGKS_TANG_ROW
+template <typename T>
+__device__ __forceinline__ const T* tang_table(int m);
+template <>
+__device__ __forceinline__ const double* tang_table<double>(int m) {
+  return kTangW64[m];
+}
+template <>
+__device__ __forceinline__ const float* tang_table<float>(int m) {
+  return kTangW32[m];
+}
+
+// Phase 2 data: tangential fourth-order reconstruction, for the t1 Gauss point m
+// and both t2 Gauss points l, of Q0 (value, d/dt1, d/dt2) and of dQ0/dn (value)
+// from the 5 x 5 face neighbourhood whose corner sits at LDS index `corner`.
+// Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).  i1 is the
+// t1 metric factor at this Gauss point, i2m / i2p the t2 factors at l = 0 / 1.
+template <typename T, int DIR>
+__device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2m, T i2p, T (*Qg)[5],
+                                        T (*Dg)[3][5]) {
+  using TG = TileGeom<DIR>;
+  constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
+  constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
+  // the rows (t1 lines) are needed at one t1 Gauss point only: weighted sums
+  // with that point's weights (15 FMAs per row) instead of both points' values;
+  // the weights come from a constant table indexed by the uniform m (scalar loads)
+  const T* wv = tang_table<T>(m);
+  const T* wd = wv + 5;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    // keep the scheduler from hoisting the next component's LDS reads: it would
+    // otherwise hold all 250 values at once and drop the occupancy to one wave
+    asm volatile("" ::: "memory");
+    const T* f0 = ff + k * TG::NFF + corner;
+    const T* fn = ff + (5 + k) * TG::NFF + corner;
+    T rv[5], rd[5], rn[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      T v = wv[0] * f0[r * s2], d = wd[0] * f0[r * s2], n = wv[0] * fn[r * s2];
+#pragma unroll
+      for (int a = 1; a < 5; ++a) {
+        const T x = f0[a * s1 + r * s2], y = fn[a * s1 + r * s2];
+        v = v + wv[a] * x;
+        d = d + wd[a] * x;
+        n = n + wv[a] * y;
+      }
+      rv[r] = v;
+      rd[r] = d;
+      rn[r] = n;
+    }
+    T vm, vp, d2m, d2p, d1m, d1p, nm, np;
+    tang_val(rv, vm, vp);
+    tang_der(rv, d2m, d2p);
+    tang_val(rd, d1m, d1p);
+    tang_val(rn, nm, np);
+    Qg[0][k] = vm;
+    Qg[1][k] = vp;
+    Dg[0][0][k] = nm;
+    Dg[1][0][k] = np;
+    Dg[0][1][k] = d1m * i1;
+    Dg[1][1][k] = d1p * i1;
+    Dg[0][2][k] = d2m * i2m;
+    Dg[1][2][k] = d2p * i2p;
+  }
 }
 
 }  // namespace hgks
