@@ -30,22 +30,30 @@ __device__ __forceinline__ void global_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tiles of the adjoint kernels: as the forward ones, except x-faces, whose
+// forward 4 x 8 x 8 tile would need 92 KB of LDS here (face field and its
+// cotangent) and leave one block per CU; 2 x 16 x 8 needs 77 KB (two blocks).
+template <int DIR> struct AdjTile { static constexpr int B[3] = {FluxTile<DIR>::B[0], FluxTile<DIR>::B[1], FluxTile<DIR>::B[2]}; };
+template <> struct AdjTile<0> { static constexpr int B[3] = {2, 16, 8}; };
+template <int DIR>
+using AdjGeom = TileGeomB<DIR, AdjTile<DIR>::B[0], AdjTile<DIR>::B[1], AdjTile<DIR>::B[2]>;
+
 template <int DIR, bool NEED_F>
-__global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __restrict__ q,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) flux_vjp_kernel(Geo g, const double* __restrict__ q,
                                                        const double* __restrict__ A, const double* __restrict__ B,
                                                        double cLA, double cLB, double cDA, double cDB,
                                                        double* __restrict__ lam, int ntx, int nty, int ntz, int nper) {
   using T = double;
-  using TG = TileGeom<DIR>;
+  using TG = AdjGeom<DIR>;
   __shared__ T ff[10 * TG::NFF];
   __shared__ T ffb[10 * TG::NFF];
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
-  tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
+  tile_origin<DIR, TG>(tile, ntx, nty, ntz, x0, y0, z0);
   const int tid = threadIdx.x;
 
-  face_field_tile<T, DIR>(g, q, ff, x0, y0, z0, g.inv_h[DIR]);
+  face_field_tile<T, DIR, false, TG>(g, q, ff, x0, y0, z0, g.inv_h[DIR]);
   for (int e = tid; e < 10 * TG::NFF; e += 256) ffb[e] = T(0);
   __syncthreads();
 
@@ -77,7 +85,7 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
 #pragma unroll 1
       for (int m = 0; m < 2; ++m) {
         T Qg[2][5], Dg[2][3][5];
-        gp_data<T, DIR>(ff, corner, m, i1, i2, i2, Qg, Dg);
+        gp_data<T, DIR, TG>(ff, corner, m, i1, i2, i2, Qg, Dg);
         T Qgb[2][5], Dgb[2][3][5];
 #pragma unroll
         for (int l = 0; l < 2; ++l) {
@@ -86,6 +94,8 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
             Qgb[l][k] = T(0);
             Dgb[l][0][k] = Dgb[l][1][k] = Dgb[l][2][k] = T(0);
           }
+          // one Gauss point at a time: the second reverse sweep waits for the first
+          if (l == 1) zdep(Qg[1][0], Qgb[0][0]);
           smooth_flux_vjp<NEED_F, false>(g, Qg[l], Dg[l], Fb, dFb, Qgb[l], Dgb[l]);
         }
         // transpose of the tangential reconstruction for this m
@@ -115,8 +125,15 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
   }
   __syncthreads();
 
-  // ---- phase 3: per face-field entry, reverse compatibility + normal reconstruction
+  // ---- phase 3a: per face-field entry, reverse of the compatibility state.  The
+  // entry's cotangents of the normal reconstruction, l = Q_l-bar/60,
+  // r = Q_r-bar/60 and d = D_n-bar/(12 h), go to LDS: l over Q0-bar (ffb fields
+  // 0..4), d over D_n-bar (ffb fields 5..9), r into the face field's space, which
+  // is not read any more.
   const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
+  T* cl = ffb;
+  T* cd = ffb + 5 * TG::NFF;
+  T* cr = ff;
   for (int e = tid; e < TG::NFF; e += 256) {
     T Q0b[5], Dnb[5];
     bool any = false;
@@ -126,40 +143,70 @@ __global__ void __launch_bounds__(256) flux_vjp_kernel(Geo g, const double* __re
       Dnb[k] = ffb[(5 + k) * TG::NFF + e];
       any = any || Q0b[k] != T(0) || Dnb[k] != T(0);
     }
-    if (!any) continue;
-    T v[5][6];
-    long long off[6];
-    normal_stencil<T, DIR>(g, q, e, x0, y0, z0, v, off);
-    T Ql[5], Qr[5], Dn[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
     T Qlb[5] = {0, 0, 0, 0, 0}, Qrb[5] = {0, 0, 0, 0, 0};
-    compat_dev_vjp(g, Ql, Qr, Q0b, Qlb, Qrb);
+    if (any) {
+      T v[5][6];
+      long long off[6];
+      normal_stencil<T, DIR, false, TG>(g, q, e, x0, y0, z0, v, off);
+      T Ql[5], Qr[5], Dn[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
+      compat_dev_vjp(g, Ql, Qr, Q0b, Qlb, Qrb);
+    }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      T vb[6];
-      const T l = Qlb[k] * T(1.0 / 60.0), r = Qrb[k] * T(1.0 / 60.0), d = Dnb[k] * ih12;
-      vb[0] = T(2) * l;
-      vb[1] = T(-13) * l - T(3) * r + d;
-      vb[2] = T(47) * l + T(27) * r - T(15) * d;
-      vb[3] = T(27) * l + T(47) * r + T(15) * d;
-      vb[4] = T(-3) * l - T(13) * r - d;
-      vb[5] = T(2) * r;
-      double* out = lam + (long long)gcomp_local<DIR>(k) * g.N;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) global_add(out + off[j], vb[j]);
+      cl[k * TG::NFF + e] = Qlb[k] * T(1.0 / 60.0);
+      cr[k * TG::NFF + e] = Qrb[k] * T(1.0 / 60.0);
+      cd[k * TG::NFF + e] = Dnb[k] * ih12;
     }
   }
-}
+  __syncthreads();
 
-template <int DIR>
-void tile_grid(const Geo& g, int& ntx, int& nty, int& ntz, int& nper);
+  // ---- phase 3b: per cell of the tile's footprint (the faces' normal extent plus
+  // the five further cells of the six-cell stencil, times the tangential patch),
+  // the transpose of the normal reconstruction gathered over the entries whose
+  // stencil holds the cell, then one atomic add per component.  The weights of
+  // stencil position m = 0..5 (cells n-2 .. n+3 of face n+1/2) are
+  //   l (2, -13, 47, 27, -3, 0) + r (0, -3, 27, 47, -13, 2) + d (0, 1, -15, 15, -1, 0).
+  constexpr int BN = DIR == 0 ? TG::BX : (DIR == 1 ? TG::BY : TG::BZ);
+  constexpr int PX = DIR == 0 ? BN + 5 : TG::FX;
+  constexpr int PY = DIR == 1 ? BN + 5 : TG::FY;
+  constexpr int PZ = DIR == 2 ? BN + 5 : TG::FZ;
+  for (int c = tid; c < PX * PY * PZ; c += 256) {
+    const int px = c % PX, py = (c / PX) % PY, pz = c / (PX * PY);
+    const int pc[3] = {px, py, pz};
+    const int pn = pc[DIR];
+    // global cell: the normal axis starts two cells before the tile's first face
+    // row, the tangential axes at the patch origin (halo of two)
+    const int gc[3] = {wrapmod(x0 - 2 + px, g.n[0]), wrapmod(y0 - 2 + py, g.n[1]), wrapmod(z0 - 2 + pz, g.n[2])};
+    const long long cell = (long long)gc[0] + (long long)gc[1] * g.stride[1] + (long long)gc[2] * g.stride[2];
+    T acc[5] = {0, 0, 0, 0, 0};
+    const int ilo = pn - 5 > 0 ? pn - 5 : 0, ihi = pn < BN - 1 ? pn : BN - 1;
+    for (int i = ilo; i <= ihi; ++i) {
+      int ec[3] = {px, py, pz};
+      ec[DIR] = i;
+      const int e = ec[0] + TG::FX * (ec[1] + TG::FY * ec[2]);
+      const int m = pn - i;
+      const T wl = m == 0 ? T(2) : m == 1 ? T(-13) : m == 2 ? T(47) : m == 3 ? T(27) : m == 4 ? T(-3) : T(0);
+      const T wr = m == 1 ? T(-3) : m == 2 ? T(27) : m == 3 ? T(47) : m == 4 ? T(-13) : m == 5 ? T(2) : T(0);
+      const T wd = m == 1 ? T(1) : m == 2 ? T(-15) : m == 3 ? T(15) : m == 4 ? T(-1) : T(0);
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        acc[k] += wl * cl[k * TG::NFF + e] + wr * cr[k * TG::NFF + e] + wd * cd[k * TG::NFF + e];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) global_add(lam + (long long)gcomp_local<DIR>(k) * g.N + cell, acc[k]);
+  }
+}
 
 template <int DIR, bool NEED_F>
 static void launch_vjp_dir(const Geo& g, const double* q, const double* A, const double* B, double cLA, double cLB,
                            double cDA, double cDB, double* lam, hipStream_t st) {
-  int ntx, nty, ntz, nper;
-  tile_grid<DIR>(g, ntx, nty, ntz, nper);
+  using TG = AdjGeom<DIR>;
+  const int ntx = (g.n[0] + TG::BX - 1) / TG::BX;
+  const int nty = (g.n[1] + TG::BY - 1) / TG::BY;
+  const int ntz = (g.n[2] + TG::BZ - 1) / TG::BZ;
+  const int nper = (ntx * nty * ntz + 7) / 8;
   flux_vjp_kernel<DIR, NEED_F><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, A, B, cLA, cLB, cDA, cDB, lam,
                                                                                 ntx, nty, ntz, nper);
 }

@@ -115,6 +115,19 @@ struct Ctrl {
   double dt_hist[kDtHist];         // time step of each step of the current call
 };
 
+// Value-dependency barrier: x is treated as recomputed from `after`, so work that
+// uses x cannot be scheduled before `after` is available.  Used to keep
+// independent stages of a long computation from being interleaved by the
+// scheduler (which would keep both stages' temporaries live at once).
+template <typename T, typename U>
+__host__ __device__ __forceinline__ void zdep(T& x, const U& after) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x) : "v"(after));
+#else
+  (void)after;
+#endif
+}
+
 __host__ __device__ __forceinline__ int wrapi(int i, int n) {
   i = i < 0 ? i + n : i;
   return i >= n ? i - n : i;

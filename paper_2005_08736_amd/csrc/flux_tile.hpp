@@ -20,15 +20,18 @@ template <> struct FluxTile<0> { static constexpr int B[3] = {4, 8, 8}; };
 template <> struct FluxTile<1> { static constexpr int B[3] = {32, 1, 8}; };
 template <> struct FluxTile<2> { static constexpr int B[3] = {32, 8, 1}; };
 
-template <int DIR>
-struct TileGeom {
-  static constexpr int BX = FluxTile<DIR>::B[0], BY = FluxTile<DIR>::B[1], BZ = FluxTile<DIR>::B[2];
+// Geometry of a tile of BX_ x BY_ x BZ_ faces of direction DIR with its halo.
+template <int DIR, int BX_, int BY_, int BZ_>
+struct TileGeomB {
+  static constexpr int BX = BX_, BY = BY_, BZ = BZ_;
   static constexpr int HX = DIR == 0 ? 0 : 2, HY = DIR == 1 ? 0 : 2, HZ = DIR == 2 ? 0 : 2;
   static constexpr int FX = BX + 2 * HX, FY = BY + 2 * HY, FZ = BZ + 2 * HZ;
   static constexpr int NFF = FX * FY * FZ;
   static constexpr int S[3] = {1, FX, FX * FY};  // LDS strides of the face-field tile
   static_assert(BX * BY * BZ == 256, "one face per thread");
 };
+template <int DIR>
+using TileGeom = TileGeomB<DIR, FluxTile<DIR>::B[0], FluxTile<DIR>::B[1], FluxTile<DIR>::B[2]>;
 
 __device__ __forceinline__ int wrapmod(int i, int n) {
   int r = i % n;
@@ -49,9 +52,8 @@ __device__ __forceinline__ int tile_of_block(int nper) { return int(blockIdx.x %
 // fastest: the next tile along the normal shares five of the six stencil planes,
 // and the blocks resident on one XCD at a time (a contiguous range of tiles)
 // cover a short column of planes that stays in its L2.
-template <int DIR>
+template <int DIR, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
-  using TG = TileGeom<DIR>;
   if (DIR == 0) {
     x0 = (tile % ntx) * TG::BX;
     const int r = tile / ntx;
@@ -75,10 +77,9 @@ __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz,
 // offsets of the six cells are returned in off.  Periodic axes wrap; with WALL,
 // y is not periodic and rows outside [0, ny) are wall ghosts (their offsets are
 // those of the mirror cells).
-template <typename T, int DIR, bool WALL = false>
+template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void normal_stencil(const Geo& g, const double* __restrict__ q, int e, int x0, int y0,
                                                int z0, T (*v)[6], long long* off) {
-  using TG = TileGeom<DIR>;
   const int ex = e % TG::FX, ey = (e / TG::FX) % TG::FY, ez = e / (TG::FX * TG::FY);
   if (!WALL) {
     int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), wrapmod(y0 + ey - TG::HY, g.n[1]),
@@ -131,15 +132,14 @@ __host__ __device__ __forceinline__ void normal_recon(const T* v, T ih12, T& ql,
 // tangential halo into ff[10][NFF].  dn_scale is 1/h of the normal axis (for
 // y-faces of a stretched mesh, 1/(y' h) at the tile's face row).  The caller
 // synchronizes.
-template <typename T, int DIR, bool WALL = false>
+template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __restrict__ q, T* ff, int x0, int y0,
                                                 int z0, double dn_scale) {
-  using TG = TileGeom<DIR>;
   const T ih12 = T(dn_scale * (1.0 / 12.0));
   for (int e = threadIdx.x; e < TG::NFF; e += 256) {
     T v[5][6];
     long long off[6];
-    normal_stencil<T, DIR, WALL>(g, q, e, x0, y0, z0, v, off);
+    normal_stencil<T, DIR, WALL, TG>(g, q, e, x0, y0, z0, v, off);
     T Ql[5], Qr[5], Dn[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
@@ -193,10 +193,9 @@ __device__ __forceinline__ const float* tang_table<float>(int m) {
 // from the 5 x 5 face neighbourhood whose corner sits at LDS index `corner`.
 // Qg[l][k] = Q0 deviation, Dg[l][a][k] = dQ0_k/dx_a along (n, t1, t2).  i1 is the
 // t1 metric factor at this Gauss point, i2m / i2p the t2 factors at l = 0 / 1.
-template <typename T, int DIR>
+template <typename T, int DIR, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T i2m, T i2p, T (*Qg)[5],
                                         T (*Dg)[3][5]) {
-  using TG = TileGeom<DIR>;
   constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
   constexpr int s1 = TG::S[A1], s2 = TG::S[A2];
   // the rows (t1 lines) are needed at one t1 Gauss point only: weighted sums

@@ -9,19 +9,6 @@
 
 namespace hgks {
 
-// Value-dependency barrier: x is treated as recomputed from `after`, so work that
-// uses x cannot be scheduled before `after` is available.  Used to keep
-// independent stages of a long computation from being interleaved by the
-// scheduler (which would keep both stages' temporaries live at once).
-template <typename T, typename U>
-__host__ __device__ __forceinline__ void zdep(T& x, const U& after) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" : "+v"(x) : "v"(after));
-#else
-  (void)after;
-#endif
-}
-
 // ---------------------------------------------------------------------------
 // WENO-Z on five cell averages v[0..4] (cell 2 in the middle).
 //
