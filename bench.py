@@ -42,9 +42,9 @@ FLUX_STAGE1_FLOPS_PER_FACE = 639 + 2320
 # from two rocprofv3 --pmc passes, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the
 # factors make the same counters read the known 671 MB in / 671 MB out of the
 # library's copy kernel.  Valid only for the kernel sources with this digest
-# (profiles/flux_fused_tgv256_counters.md).
-FLUX_STAGE1_HBM_BYTES_PER_FACE = 174.3
-FLUX_COUNTERS_SOURCE_DIGEST = "3ea2dce5ef51b37f"
+# (profiles/flux_fused_tgv256_kernels.md).
+FLUX_STAGE1_HBM_BYTES_PER_FACE = 182.3
+FLUX_COUNTERS_SOURCE_DIGEST = "fb13b38d47cc5f3c"
 
 
 def kernel_source_digest():

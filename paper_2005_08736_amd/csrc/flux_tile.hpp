@@ -48,10 +48,10 @@ __host__ __device__ __forceinline__ int gcomp_local(int local) {
 // XCD-aware tile order: block b runs on XCD b % 8 and takes tile (b % 8) * nper + b / 8
 __device__ __forceinline__ int tile_of_block(int nper) { return int(blockIdx.x % 8u) * nper + int(blockIdx.x / 8u); }
 
-// Origin (first face) of a tile.  Tiles are numbered with the normal axis
-// fastest: the next tile along the normal shares five of the six stencil planes,
-// and the blocks resident on one XCD at a time (a contiguous range of tiles)
-// cover a short column of planes that stays in its L2.
+// Origin (first face) of a tile.  x- and z-face tiles are numbered with the
+// normal axis fastest: the next tile along the normal shares five of the six
+// stencil planes, and the blocks resident on one XCD at a time (a contiguous
+// range of tiles) cover a short column of planes that stays in its L2.
 template <int DIR, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
   if (DIR == 0) {
@@ -60,10 +60,12 @@ __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz,
     y0 = (r % nty) * TG::BY;
     z0 = (r / nty) * TG::BZ;
   } else if (DIR == 1) {
-    y0 = (tile % nty) * TG::BY;
-    const int r = tile / nty;
-    x0 = (r % ntx) * TG::BX;
-    z0 = (r / ntx) * TG::BZ;
+    // y-faces: x first, then y (a y-face tile is one row thick, so the next row
+    // follows after ntx tiles); walking y first doubled the HBM fetch
+    x0 = (tile % ntx) * TG::BX;
+    const int r = tile / ntx;
+    y0 = (r % nty) * TG::BY;
+    z0 = (r / nty) * TG::BZ;
   } else {
     z0 = (tile % ntz) * TG::BZ;
     const int r = tile / ntz;

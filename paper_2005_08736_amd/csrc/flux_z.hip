@@ -234,8 +234,15 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   }
 }
 
+#ifndef HGKS_ZWAVES
+#define HGKS_ZWAVES 2
+#endif
+#ifndef HGKS_ZWAVES_F32
+#define HGKS_ZWAVES_F32 4
+#endif
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_ZWAVES : HGKS_ZWAVES_F32)))
 flux_z_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
               const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   if (*stop) return;
