@@ -80,11 +80,11 @@ def cpu_baseline(n_cpu: int, steps: int):
     }
 
 
-def adjoint_timing(r, reps, torch):
+def adjoint_timing(r, reps, torch, label):
     """Time of one step adjoint (hgks_step_vjp, which recomputes the first stage
-    itself) at the current state of the FP64 run, and the cost of a reverse step
-    under checkpointing (the forward recompute of the step's input plus its
-    adjoint) relative to a forward step."""
+    itself) at the current state of a run, in that run's arithmetic, and the cost
+    of a reverse step under checkpointing (the forward recompute of the step's
+    input plus its adjoint) relative to a forward step of the same form."""
     s, q = r["solver"], r["q"]
     dt = float(r["dts"][-1])
     gen = torch.Generator(device=q.device).manual_seed(0)
@@ -110,9 +110,9 @@ def adjoint_timing(r, reps, torch):
         "ratio_vs_forward_step": (el * 1e3 + r["ms"]) / r["ms"],
         "vjp_only_ratio": el * 1e3 / r["ms"],
         "operator_vjp_avg_launch_ms": ms_vjp / max(cnt_vjp, 1),
-        "workload": "same state and step as the forward run, FP64, dt frozen",
+        "workload": f"same state and step as the forward run, {label}, dt frozen",
     }
-    log(f"[bench] adjoint: {el * 1e3:.3f} ms per step VJP; reverse step with recompute / forward step = "
+    log(f"[bench] adjoint ({label}): {el * 1e3:.3f} ms per step VJP; reverse step with recompute / forward step = "
         f"{out['ratio_vs_forward_step']:.2f}; operator_vjp {out['operator_vjp_avg_launch_ms']:.3f} ms per launch")
     return out
 
@@ -223,8 +223,9 @@ def main():
         return dict(value=value, ms=el / args.steps * 1e3, prof=prof, dts=dts, solver=s, q=q)
 
     r64 = run(hgks.PREC_F64)
-    adj = adjoint_timing(r64, args.adjoint_reps, torch)
+    adj = adjoint_timing(r64, args.adjoint_reps, torch, "FP64")
     r32 = run(hgks.PREC_F32FLUX)
+    adj["fp32_form"] = adjoint_timing(r32, args.adjoint_reps, torch, "FP32-flux form")
     others = other_workloads(args, torch, np, cases, hgks, dev) if args.other_steps > 0 else None
     value = r64["value"]
     ms_per_step = r64["ms"]

@@ -38,15 +38,18 @@ template <> struct AdjTile<0> { static constexpr int B[3] = {2, 16, 8}; };
 template <int DIR>
 using AdjGeom = TileGeomB<DIR, AdjTile<DIR>::B[0], AdjTile<DIR>::B[1], AdjTile<DIR>::B[2]>;
 
-template <int DIR, bool NEED_F>
+// T is the arithmetic of the recomputed forward and of its reverse (double, or
+// float for the FP32-flux form); the cotangents A, B and lambda stay in double.
+template <typename T, int DIR, bool NEED_F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) flux_vjp_kernel(Geo g, const double* __restrict__ q,
                                                        const double* __restrict__ A, const double* __restrict__ B,
                                                        double cLA, double cLB, double cDA, double cDB,
                                                        double* __restrict__ lam, int ntx, int nty, int ntz, int nper) {
-  using T = double;
   using TG = AdjGeom<DIR>;
   __shared__ T ff[10 * TG::NFF];
-  __shared__ T ffb[10 * TG::NFF];
+  // the cotangent tile accumulates in double in both forms: LDS atomic adds of
+  // FP32 stalled the FP32 kernel on LDS waits five times over the FP64 one
+  __shared__ double ffb[10 * TG::NFF];
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
@@ -54,7 +57,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
   const int tid = threadIdx.x;
 
   face_field_tile<T, DIR, false, TG>(g, q, ff, x0, y0, z0, g.inv_h[DIR]);
-  for (int e = tid; e < 10 * TG::NFF; e += 256) ffb[e] = T(0);
+  for (int e = tid; e < 10 * TG::NFF; e += 256) ffb[e] = 0.0;
   __syncthreads();
 
   // ---- phase 2: per face
@@ -72,15 +75,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
       int c[3] = {gx, gy, gz};
       const long long up = c[DIR] == g.n[DIR] - 1 ? idx - (long long)(g.n[DIR] - 1) * g.stride[DIR]
                                                   : idx + g.stride[DIR];
+      // (formed in double, then rounded once to T)
       T Fb[5], dFb[5];
-      const T w = T(0.25 * g.inv_h[DIR]);
+      const double w = 0.25 * g.inv_h[DIR];
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
         const long long o = (long long)gcomp_local<DIR>(k) * g.N;
-        T a = A[o + up] - A[o + idx];
-        T b = B ? B[o + up] - B[o + idx] : T(0);
-        Fb[k] = NEED_F ? w * (T(cLA) * a + T(cLB) * b) : T(0);
-        dFb[k] = w * (T(cDA) * a + T(cDB) * b);
+        const double a = A[o + up] - A[o + idx];
+        const double b = B ? B[o + up] - B[o + idx] : 0.0;
+        Fb[k] = NEED_F ? T(w * (cLA * a + cLB * b)) : T(0);
+        dFb[k] = T(w * (cDA * a + cDB * b));
       }
 #pragma unroll 1
       for (int m = 0; m < 2; ++m) {
@@ -105,8 +109,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
         tang_weights(1, wv1, wd1);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          T* f0b = ffb + k * TG::NFF + corner;
-          T* fnb = ffb + (5 + k) * TG::NFF + corner;
+          double* f0b = ffb + k * TG::NFF + corner;
+          double* fnb = ffb + (5 + k) * TG::NFF + corner;
 #pragma unroll
           for (int r = 0; r < 5; ++r) {
             // cotangents of the row values at (m, row r): value, t1-derivative, normal slope
@@ -115,8 +119,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
             T rn = wv0[r] * Dgb[0][0][k] + wv1[r] * Dgb[1][0][k];
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-              lds_add(f0b + a * s1 + r * s2, wvm[a] * rv + wdm[a] * rd);
-              lds_add(fnb + a * s1 + r * s2, wvm[a] * rn);
+              lds_add(f0b + a * s1 + r * s2, double(wvm[a] * rv + wdm[a] * rd));
+              lds_add(fnb + a * s1 + r * s2, double(wvm[a] * rn));
             }
           }
         }
@@ -131,16 +135,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
   // 0..4), d over D_n-bar (ffb fields 5..9), r into the face field's space, which
   // is not read any more.
   const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
-  T* cl = ffb;
-  T* cd = ffb + 5 * TG::NFF;
+  double* cl = ffb;
+  double* cd = ffb + 5 * TG::NFF;
   T* cr = ff;
   for (int e = tid; e < TG::NFF; e += 256) {
     T Q0b[5], Dnb[5];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      Q0b[k] = ffb[k * TG::NFF + e];
-      Dnb[k] = ffb[(5 + k) * TG::NFF + e];
+      Q0b[k] = T(ffb[k * TG::NFF + e]);
+      Dnb[k] = T(ffb[(5 + k) * TG::NFF + e]);
       any = any || Q0b[k] != T(0) || Dnb[k] != T(0);
     }
     T Qlb[5] = {0, 0, 0, 0, 0}, Qrb[5] = {0, 0, 0, 0, 0};
@@ -180,7 +184,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
     // row, the tangential axes at the patch origin (halo of two)
     const int gc[3] = {wrapmod(x0 - 2 + px, g.n[0]), wrapmod(y0 - 2 + py, g.n[1]), wrapmod(z0 - 2 + pz, g.n[2])};
     const long long cell = (long long)gc[0] + (long long)gc[1] * g.stride[1] + (long long)gc[2] * g.stride[2];
-    T acc[5] = {0, 0, 0, 0, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
     const int ilo = pn - 5 > 0 ? pn - 5 : 0, ihi = pn < BN - 1 ? pn : BN - 1;
     for (int i = ilo; i <= ihi; ++i) {
       int ec[3] = {px, py, pz};
@@ -195,11 +199,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
         acc[k] += wl * cl[k * TG::NFF + e] + wr * cr[k * TG::NFF + e] + wd * cd[k * TG::NFF + e];
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) global_add(lam + (long long)gcomp_local<DIR>(k) * g.N + cell, acc[k]);
+    for (int k = 0; k < 5; ++k) global_add(lam + (long long)gcomp_local<DIR>(k) * g.N + cell, double(acc[k]));
   }
 }
 
-template <int DIR, bool NEED_F>
+template <typename T, int DIR, bool NEED_F>
 static void launch_vjp_dir(const Geo& g, const double* q, const double* A, const double* B, double cLA, double cLB,
                            double cDA, double cDB, double* lam, hipStream_t st) {
   using TG = AdjGeom<DIR>;
@@ -207,24 +211,32 @@ static void launch_vjp_dir(const Geo& g, const double* q, const double* A, const
   const int nty = (g.n[1] + TG::BY - 1) / TG::BY;
   const int ntz = (g.n[2] + TG::BZ - 1) / TG::BZ;
   const int nper = (ntx * nty * ntz + 7) / 8;
-  flux_vjp_kernel<DIR, NEED_F><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, A, B, cLA, cLB, cDA, cDB, lam,
+  flux_vjp_kernel<T, DIR, NEED_F><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, A, B, cLA, cLB, cDA, cDB, lam,
                                                                                 ntx, nty, ntz, nper);
 }
 
-// lam += (dL/dQ)^T mu_L + (ddL/dQ)^T mu_dL at state q for the faces of direction
-// dir, with mu_L = cLA A + cLB B and mu_dL = cDA A + cDB B (B may be null).
-void launch_operator_vjp(const Geo& g, int dir, const double* q, const double* A, const double* B, double cLA,
-                         double cLB, double cDA, double cDB, double* lam, hipStream_t st) {
+template <typename T>
+static void operator_vjp_t(const Geo& g, int dir, const double* q, const double* A, const double* B, double cLA,
+                           double cLB, double cDA, double cDB, double* lam, hipStream_t st) {
   const bool need_f = cLA != 0.0 || cLB != 0.0;
   if (need_f) {
-    if (dir == 0) launch_vjp_dir<0, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    else if (dir == 1) launch_vjp_dir<1, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    else launch_vjp_dir<2, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    if (dir == 0) launch_vjp_dir<T, 0, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else if (dir == 1) launch_vjp_dir<T, 1, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else launch_vjp_dir<T, 2, true>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
   } else {
-    if (dir == 0) launch_vjp_dir<0, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    else if (dir == 1) launch_vjp_dir<1, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
-    else launch_vjp_dir<2, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    if (dir == 0) launch_vjp_dir<T, 0, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else if (dir == 1) launch_vjp_dir<T, 1, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+    else launch_vjp_dir<T, 2, false>(g, q, A, B, cLA, cLB, cDA, cDB, lam, st);
   }
+}
+
+// lam += (dL/dQ)^T mu_L + (ddL/dQ)^T mu_dL at state q for the faces of direction
+// dir, with mu_L = cLA A + cLB B and mu_dL = cDA A + cDB B (B may be null).  With
+// f32 the forward recompute and its reverse run in FP32 (the FP32-flux form).
+void launch_operator_vjp(const Geo& g, int dir, bool f32, const double* q, const double* A, const double* B,
+                         double cLA, double cLB, double cDA, double cDB, double* lam, hipStream_t st) {
+  if (f32) operator_vjp_t<float>(g, dir, q, A, B, cLA, cLB, cDA, cDB, lam, st);
+  else operator_vjp_t<double>(g, dir, q, A, B, cLA, cLB, cDA, cDB, lam, st);
 }
 
 // out = a * X + b * Y (elementwise over n doubles)
