@@ -131,12 +131,15 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
  * adjoint of the face-flux kernels (Gauss-point flux, tangential and normal
  * reconstruction, compatibility state) and of the stage formulas.  Device
  * atomics accumulate the cell cotangents, so repeated calls agree to rounding,
- * not bitwise.  Smooth mode with constant viscosity; with the FP32-flux form
- * the recomputed forward and its reverse run in FP32 (the adjoint of that
- * form's fluxes), the cotangents and their accumulation in FP64.
- * HGKS_E_UNSUPPORTED otherwise (mode Z, mu(T), walls, stretching, body force).
- * Enqueued on the handle's stream, no synchronization; the bound state is not
- * touched. */
+ * not bitwise.  Smooth mode: constant viscosity, FP64 or the FP32-flux form
+ * (whose recomputed forward and reverse run in FP32, the cotangents and their
+ * accumulation in FP64).  Mode Z (WENO-Z with its smooth nonlinear weights and
+ * the full flux integrated over dt, Eq. (flux)): FP64, constant viscosity or
+ * mu(T); |b0 - b2| in the Z weights and |p_l - p_r| in the collision time take
+ * the derivative sign(x) with sign(0) = +1.  HGKS_E_UNSUPPORTED otherwise (mode
+ * Z with the FP32-flux form, mu(T) in smooth mode, walls, stretching, body
+ * force).  Enqueued on the handle's stream, no synchronization; the bound state
+ * is not touched. */
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
 
 /* Global FP64 diagnostics of the bound state (Sec. 3.1, 3.4): out (host) receives

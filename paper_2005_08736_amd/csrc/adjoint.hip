@@ -21,15 +21,6 @@
 
 namespace hgks {
 
-template <typename T>
-__device__ __forceinline__ void lds_add(T* p, T v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void global_add(double* p, double v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Tiles of the adjoint kernels: as the forward ones, except x-faces, whose
 // forward 4 x 8 x 8 tile would need 92 KB of LDS here (face field and its
 // cotangent) and leave one block per CU; 2 x 16 x 8 needs 77 KB (two blocks).

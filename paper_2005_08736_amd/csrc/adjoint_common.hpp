@@ -336,4 +336,14 @@ __host__ __device__ __forceinline__ void compat_dev_vjp(const Geo& g, const T* d
   side_state_vjp(g, dQr, r, rb, dQrb);
 }
 
+// Cotangent accumulation: LDS (one workgroup) and device memory (all of them).
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void global_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace hgks

@@ -20,122 +20,10 @@
 // Tiles are numbered with the normal axis fastest (neighbouring tiles along the
 // normal share five of their six stencil planes) and dealt to the XCDs in
 // contiguous ranges.
-#include "flux_tile.hpp"
 #include "internal.hpp"
-#include "zflux.hpp"
+#include "ztile.hpp"
 
 namespace hgks {
-
-template <int DIR>
-struct ZTileGeom {
-  static constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;  // t1, t2 axes
-  static constexpr int B = 8;                                   // faces per tangential axis
-  static constexpr int P = B + 4;                               // with the halo
-  static constexpr int NFF = P * P;                             // face-field entries (t1 fastest)
-  static constexpr int NROW = B * P;                            // t1 lines (t1 in the tile, t2 with halo)
-  static constexpr int NF = 30;                                 // fields per entry
-};
-
-// field numbering in LDS
-constexpr int kZQ0 = 0, kZDn = 5, kZQl = 10, kZQr = 15, kZDl = 20, kZDr = 25;
-
-template <typename T, int DIR>
-__device__ __forceinline__ void zface_field(const Geo& g, const double* __restrict__ q, T* ff, int on, int o1, int o2) {
-  using TG = ZTileGeom<DIR>;
-  const T ih = T(g.inv_h[DIR]);
-  const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
-  const T eps = T(g.weno_eps);
-  for (int e = threadIdx.x; e < TG::NFF; e += 256) {
-    const int i1 = e % TG::P, i2 = e / TG::P;
-    int c[3];
-    c[DIR] = on;
-    c[TG::A1] = wrapmod(o1 + i1 - 2, g.n[TG::A1]);
-    c[TG::A2] = wrapmod(o2 + i2 - 2, g.n[TG::A2]);
-    const int Nn = g.n[DIR];
-    const long long sn = g.stride[DIR];
-    const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
-                           (long long)on * sn;
-    T Ql[5], Qr[5], Dl[5], Dr[5], Dn[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double* f = q + (long long)gcomp_local<DIR>(k) * g.N;
-      const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
-      T v[6];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) v[m] = T(f[base + (long long)wrapi(on - 2 + m, Nn) * sn] - ref);
-      T sl, sr;
-      weno_z_right(v, eps, g.weno_p, Ql[k], sl);
-      T rv[5] = {v[5], v[4], v[3], v[2], v[1]};
-      weno_z_right(rv, eps, g.weno_p, Qr[k], sr);
-      Dl[k] = sl * ih;
-      Dr[k] = -sr * ih;
-      Dn[k] = (v[1] - T(15) * v[2] + T(15) * v[3] - v[4]) * ih12;
-    }
-    T Q0[5];
-    compat_dev(g, Ql, Qr, Q0);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      ff[(kZQ0 + k) * TG::NFF + e] = Q0[k];
-      ff[(kZDn + k) * TG::NFF + e] = Dn[k];
-      ff[(kZQl + k) * TG::NFF + e] = Ql[k];
-      ff[(kZQr + k) * TG::NFF + e] = Qr[k];
-      ff[(kZDl + k) * TG::NFF + e] = Dl[k];
-      ff[(kZDr + k) * TG::NFF + e] = Dr[k];
-    }
-  }
-}
-
-// Phase 2: WENO-Z edge values along t1 of line (a, i2): the five entries
-// (a .. a+4, i2) of the patch, centred on entry (a+2, i2).
-template <typename T, int DIR>
-__device__ __forceinline__ void zrow_edges(const Geo& g, const T* ff, T* ed) {
-  using TG = ZTileGeom<DIR>;
-  const T eps = T(g.weno_eps);
-  for (int it = threadIdx.x; it < TG::NF * TG::NROW; it += 256) {
-    const int f = it / TG::NROW, r = it % TG::NROW;
-    const int a = r % TG::B, i2 = r / TG::B;
-    const T* src = ff + f * TG::NFF + i2 * TG::P + a;
-    T line[5];
-#pragma unroll
-    for (int s = 0; s < 5; ++s) line[s] = src[s];
-    T ea, eb;
-    weno_z_edges(line, eps, g.weno_p, ea, eb);
-    ed[2 * (f * TG::NROW + r)] = ea;
-    ed[2 * (f * TG::NROW + r) + 1] = eb;
-  }
-}
-
-// Phase 3 helper: the field's value (and t2-derivative, and optionally the
-// t1-derivative) at Gauss point (sm, sl) of the face at tile position (a, t).
-template <typename T, int DIR, bool T1DER>
-__device__ __forceinline__ void zgp_field(const Geo& g, const T* ff, const T* ed, int f, int a, int t, T sm, T sl,
-                                          T& val, T& d1, T& d2, T& token) {
-  using TG = ZTileGeom<DIR>;
-  const T eps = T(g.weno_eps);
-  // one field at a time: the reads wait for the previous field's result, so the
-  // scheduler cannot interleave the fields and hold all their temporaries at once
-  zdep(a, token);
-  T rv[5], rd[5];
-#pragma unroll
-  for (int r = 0; r < 5; ++r) {
-    const T m = ff[f * TG::NFF + (t + r) * TG::P + a + 2];
-    const int li = f * TG::NROW + (t + r) * TG::B + a;
-    const T ea = ed[2 * li], eb = ed[2 * li + 1];
-    rv[r] = zpar_val(m, ea, eb, sm);
-    if (T1DER) rd[r] = zpar_der(m, ea, eb, sm);
-  }
-  T ea, eb;
-  weno_z_edges(rv, eps, g.weno_p, ea, eb);
-  val = zpar_val(rv[2], ea, eb, sl);
-  d2 = zpar_der(rv[2], ea, eb, sl) * T(g.inv_h[TG::A2]);
-  if (T1DER) {
-    weno_z_edges(rd, eps, g.weno_p, ea, eb);
-    d1 = zpar_val(rd[2], ea, eb, sl) * T(g.inv_h[TG::A1]);
-    token = d1;
-  } else {
-    token = val;
-  }
-}
 
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
 __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,

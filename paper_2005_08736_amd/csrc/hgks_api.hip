@@ -233,7 +233,10 @@ void operator_vjp(hgks_handle* h, const double* q, const double* A, const double
                   double cDA, double cDB, double* lam) {
   for (int d = 0; d < 3; ++d) {
     bool on = prof_begin(h, HGKS_KCLASS_OPERATOR_VJP);
-    launch_operator_vjp(h->geo, d, f32(h), q, A, B, cLA, cLB, cDA, cDB, lam, h->stream);
+    if (h->p.mode == HGKS_MODE_WENOZ)
+      launch_operator_vjp_z(h->geo, d, q, A, B, cLA, cLB, cDA, cDB, &h->ctrl->dt, lam, h->stream);
+    else
+      launch_operator_vjp(h->geo, d, f32(h), q, A, B, cLA, cLB, cDA, cDB, lam, h->stream);
     prof_end(h, on);
   }
 }
@@ -424,9 +427,10 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n) {
   if (!h || !q_n || !lam_np1 || !lam_n || !(dt > 0.0)) return HGKS_E_INVALID_ARG;
   if (lam_n == lam_np1 || lam_n == q_n) return HGKS_E_INVALID_ARG;
-  if (h->p.mu_exp != 0.0 || h->p.mode != HGKS_MODE_SMOOTH || h->geo.wall_y ||
-      h->geo.stretch_y || h->geo.fx != 0.0)
-    return HGKS_E_UNSUPPORTED;
+  if (h->geo.wall_y || h->geo.stretch_y || h->geo.fx != 0.0) return HGKS_E_UNSUPPORTED;
+  // smooth mode: constant viscosity, FP64 or the FP32-flux form; mode Z: FP64
+  if (h->p.mode == HGKS_MODE_SMOOTH && h->p.mu_exp != 0.0) return HGKS_E_UNSUPPORTED;
+  if (h->p.mode == HGKS_MODE_WENOZ && f32(h)) return HGKS_E_UNSUPPORTED;
   const Geo& g = h->geo;
   hipStream_t st = h->stream;
   const long long n5 = 5 * g.N;

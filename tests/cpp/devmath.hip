@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "../../paper_2005_08736_amd/csrc/adjoint_common.hpp"
+#include "../../paper_2005_08736_amd/csrc/zadjoint_common.hpp"
 #include "../../paper_2005_08736_amd/csrc/zflux.hpp"
 
 using namespace hgks;
@@ -117,6 +118,49 @@ int dm_full_flux(const double* Ql, const double* Dl, const double* Qr, const dou
       dz[a][k] = D0[a * 5 + k];
     }
   full_flux_tau(g, z, dz, l, dl, r, dr, tau, dt, F, dF);
+  return 0;
+}
+
+// Mode-Z Gauss-point flux of the 60 deviation inputs X (Q0, Q_l, Q_r, then D0,
+// D_l, D_r each [3][5]) with tau = mu(T0)/p0 + c_art |p_l - p_r|/(p_l + p_r) dt,
+// mu(T) = mu (T/T_ref)^mu_exp; and the transpose of its Jacobian applied to the
+// cotangents (Fb, dFb), from forward tangents.
+static Geo make_z(double gamma, double prandtl, double mu, double T_ref, double mu_exp, double c_art, double rho_ref,
+                  double p_ref) {
+  Geo g = make(gamma, prandtl, mu, rho_ref, p_ref);
+  g.T_ref = T_ref;
+  g.mu_exp = mu_exp;
+  g.c_art = c_art;
+  return g;
+}
+
+int dm_zgp_flux(const double* X, double dt, double gamma, double prandtl, double mu, double T_ref, double mu_exp,
+                double c_art, double rho_ref, double p_ref, double* F, double* dF) {
+  Geo g = make_z(gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref);
+  if (mu_exp != 0.0) zgp_flux<true>(g, X, dt, F, dF);
+  else zgp_flux<false>(g, X, dt, F, dF);
+  return 0;
+}
+
+int dm_zflux_jt(const double* X, double dt, double gamma, double prandtl, double mu, double T_ref, double mu_exp,
+                double c_art, double rho_ref, double p_ref, const double* Fb, const double* dFb, double* Xb) {
+  Geo g = make_z(gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref);
+  for (int c0 = 0; c0 < kXN; c0 += kZTan) {
+    if (mu_exp != 0.0) zflux_jt_columns<true>(g, X, c0, dt, Fb, dFb, Xb);
+    else zflux_jt_columns<false>(g, X, c0, dt, Fb, dFb, Xb);
+  }
+  return 0;
+}
+
+// Jacobians of the WENO-Z edge pair (J[2][5]) and of the right-edge value and
+// slope (Jv[5], Js[5]) of a five-value line
+int dm_wze_jac(const double* v, double eps, int p, double* J) {
+  wze_jac(v, eps, p, reinterpret_cast<double(*)[5]>(J));
+  return 0;
+}
+
+int dm_wzr_jac(const double* v, double eps, int p, double* Jv, double* Js) {
+  wzr_jac(v, eps, p, Jv, Js);
   return 0;
 }
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cpp", "devmath.hip")
 LIB = os.path.join(HERE, "cpp", "libdevmath.so")
 HDRS = [os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", n)
-        for n in ("device_common.hpp", "adjoint_common.hpp", "zflux.hpp")]
+        for n in ("device_common.hpp", "adjoint_common.hpp", "zflux.hpp", "tangent.hpp", "zadjoint_common.hpp")]
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -88,3 +88,36 @@ def full_flux(Ql, Dl, Qr, Dr, Q0, D0, tau, dt, gamma, prandtl, rho_ref, p_ref):
     lib().dm_full_flux(*[_p(a) for a in args], ctypes.c_double(tau), ctypes.c_double(dt), ctypes.c_double(gamma),
                        ctypes.c_double(prandtl), ctypes.c_double(rho_ref), ctypes.c_double(p_ref), _p(F), _p(dF))
     return F, dF
+
+
+def _zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref):
+    return [ctypes.c_double(v) for v in (dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref)]
+
+
+def zgp_flux(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref):
+    X = _a(X, 60)
+    F, dF = np.zeros(5), np.zeros(5)
+    lib().dm_zgp_flux(_p(X), *_zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref), _p(F), _p(dF))
+    return F, dF
+
+
+def zflux_jt(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb, dFb):
+    X, Fb, dFb = _a(X, 60), _a(Fb, 5), _a(dFb, 5)
+    Xb = np.zeros(60)
+    lib().dm_zflux_jt(_p(X), *_zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref), _p(Fb), _p(dFb),
+                      _p(Xb))
+    return Xb
+
+
+def wze_jac(v, eps, p):
+    v = _a(v, 5)
+    J = np.zeros((2, 5))
+    lib().dm_wze_jac(_p(v), ctypes.c_double(eps), ctypes.c_int(p), _p(J))
+    return J
+
+
+def wzr_jac(v, eps, p):
+    v = _a(v, 5)
+    Jv, Js = np.zeros(5), np.zeros(5)
+    lib().dm_wzr_jac(_p(v), ctypes.c_double(eps), ctypes.c_int(p), _p(Jv), _p(Js))
+    return Jv, Js

@@ -122,3 +122,69 @@ def test_device_full_flux_matches_oracle(oracle_mod, p_level):
         # dF is a second difference of the time integrals: both sides round at
         # ~1e-16 |I| / (dt |dF|) relative
         assert np.abs(dF - rdF).max() <= 1e-10 * np.abs(rdF).max(), (dF, rdF)
+
+
+def test_wenoz_jacobians_match_central_differences():
+    """The forward-tangent Jacobians of the WENO-Z edge pair and of the right-edge
+    value and slope (used by the mode-Z adjoint) against central differences, on
+    smooth, steep and near-discontinuous lines, exponents 1 and 2."""
+    lines = [rng.normal(size=5) for _ in range(20)]
+    lines += [np.array([1.0, 1.02, 1.1, 0.1, 0.0]), 1.0 + 1e-3 * np.sin(0.7 * np.arange(5) + 0.2)]
+    for v in lines:
+        for p in (1, 2):
+            J = devmath.wze_jac(v, 1e-6, p)
+            Jv, Js = devmath.wzr_jac(v, 1e-6, p)
+            # the Z weights vary on the scale of the line's own variation (and of eps)
+            h = 1e-4 * max(np.ptp(v), 1e-3)
+            for i in range(5):
+                e = np.zeros(5)
+                e[i] = 1.0
+
+                def edges(x):
+                    return np.array(devmath.weno_z_edges(x, 1e-6, p))
+
+                def right(x):
+                    return np.array(devmath.weno_z_right(x, 1e-6, p))
+
+                for f, col in ((edges, J[:, i]), (right, np.array([Jv[i], Js[i]]))):
+                    fd = np.array([_fd_check(f, v, e, w, h) for w in np.eye(2)])
+                    assert np.abs(col - fd).max() <= 1e-6 * max(np.abs(fd).max(), 1.0), (v, p, i, col, fd)
+
+
+def _z_inputs(p_level, rho_ref, p_ref):
+    """60 mode-Z Gauss-point inputs: deviations of Q0, Q_l, Q_r from the reference
+    state, then the three slope sets [3][5]."""
+    E_ref = p_ref / (GAMMA - 1)
+    ref = np.array([rho_ref, 0.0, 0.0, 0.0, E_ref])
+    Ql, Qr = states(p_level), states(p_level)
+    Q0 = 0.5 * (Ql + Qr) + 0.01 * p_level * rng.normal(size=5) * np.array([0, 0, 0, 0, 1])
+    slopes = rng.normal(size=45) * np.tile(np.array([0.1, 0.3, 0.3, 0.3, p_level]), 9)
+    return np.concatenate([Q0 - ref, Ql - ref, Qr - ref, slopes])
+
+
+@pytest.mark.parametrize("p_level,mu_exp", [(1.0, 0.0), (2.86, 0.76), (71.4, 0.0)])
+def test_zflux_jacobian_transpose_matches_central_differences(p_level, mu_exp):
+    """J^T (Fb, dFb) of the mode-Z Gauss-point flux (full distribution, time
+    integrals, collision time with the |p_l - p_r| term, mu(T)) from forward
+    tangents against central differences of <Fb, F> + <dFb, dF> along random
+    directions, dt/tau from 0.05 to 20."""
+    rho_ref, p_ref = 1.0, p_level
+    mu, c_art = 1e-3, 1.0
+    for i in range(8):
+        X = _z_inputs(p_level, rho_ref, p_ref)
+        dt = mu / p_level * [0.05, 1.0, 5.0, 20.0][i % 4]
+        Fb, dFb = rng.normal(size=5), rng.normal(size=5)
+        args = (dt, GAMMA, 0.72, mu, 1.0, mu_exp, c_art, rho_ref, p_ref)
+        Xb = devmath.zflux_jt(X, *args, Fb, dFb)
+
+        def f(x):
+            F, dF = devmath.zgp_flux(x, *args)
+            return np.concatenate([F, dF])
+
+        wb = np.concatenate([Fb, dFb])
+        for _ in range(3):
+            v = rng.normal(size=60) * np.abs(X).clip(1e-2)
+            fd = _fd_check(f, X, v, wb, 1e-5)
+            got = float(Xb @ v)
+            sc = sum(abs(_fd_check(f, X, v * (np.arange(60) == j), wb, 1e-5)) for j in range(0, 60, 7)) + abs(fd)
+            assert abs(got - fd) <= 1e-6 * sc, (i, got, fd, sc)
