@@ -19,10 +19,59 @@
 
 namespace hgks {
 
+// Phase 2 with rows shared across the tile (rows_pass / rows_combine) or, where
+// the row buffers would cost occupancy, per face (gp_data): the FP64 x-face tile
+// (4 x 8 x 8 with a 12 x 12 halo) already fills 46 KB of LDS, and 18 KB more of
+// rows drops it from three workgroups per CU to two (measured 19% slower).
+#ifndef HGKS_SHARED_ROWS_X64
+#define HGKS_SHARED_ROWS_X64 0
+#endif
+#ifndef HGKS_SHARED_ROWS_X32
+#define HGKS_SHARED_ROWS_X32 1
+#endif
+template <typename T, int DIR>
+constexpr bool kSharedRows = DIR != 0 || (sizeof(T) == 4 ? HGKS_SHARED_ROWS_X32 : HGKS_SHARED_ROWS_X64);
+template <typename T, int DIR>
+constexpr int kRowBuf = kSharedRows<T, DIR> ? 2 * RowGeom<DIR>::NBUF : 1;
+
+// Per-face phase 2: each face sums its own 5 x 5 neighbourhood (gp_data), one t1
+// Gauss point at a time; with a stretched y (channel), y is t1 of x-faces.
+template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+__device__ __forceinline__ void per_face_phase2(const Geo& g, const T* ff, const int* tp, int gy, bool ys, T* Fs,
+                                                T* dFs) {
+  static_assert(DIR == 0, "per-face phase 2 serves x-faces, whose t1 is the stretched y");
+  using TG = TileGeom<DIR>;
+  constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
+  const int centre = (tp[0] + TG::HX) + (tp[1] + TG::HY) * TG::FX + (tp[2] + TG::HZ) * TG::FX * TG::FY;
+  const int corner = centre - 2 * TG::S[A1] - 2 * TG::S[A2];
+  const T i2 = T(g.inv_h[A2]);
+#pragma unroll 1
+  for (int m = 0; m < 2; ++m) {  // t1 Gauss point (-, +)
+    T i1 = T(g.inv_h[A1]), w1 = T(1);
+    if (ys && A1 == 1) {
+      i1 = T(ym_gp_inv(g, gy, m));
+      w1 = T(ym_gp_w(g, gy, m));
+    }
+    T Qg[2][5], Dg[2][3][5];
+    gp_data<T, DIR>(ff, corner, m, i1, i2, i2, Qg, Dg);
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      T F[5], dF[5];
+      smooth_flux<!STAGE2, VAR_MU>(g, Qg[l], Dg[l], F, dF);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        if (!STAGE2) Fs[k] += ys ? w1 * F[k] : F[k];
+        dFs[k] += ys ? w1 * dF[k] : dF[k];
+      }
+    }
+  }
+}
+
 template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN>
 __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
-                                                T* ff, int ntx, int nty, int ntz, int nper) {
+                                                T* ff, T* rowbuf, int ntx, int nty, int ntz, int nper) {
   using TG = TileGeom<DIR>;
+  using RG = RowGeom<DIR>;
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
@@ -38,42 +87,59 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   const int tid = threadIdx.x;
   const int fx = tid % TG::BX, fy = (tid / TG::BX) % TG::BY, fz = tid / (TG::BX * TG::BY);
   const int gx = x0 + fx, gy = y0 + fy, gz = z0 + fz;
-  if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) return;
-  constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
-  const int centre = (fx + TG::HX) + (fy + TG::HY) * TG::FX + (fz + TG::HZ) * TG::FX * TG::FY;
-  const int corner = centre - 2 * TG::S[A1] - 2 * TG::S[A2];
-  // metric factors of the tangential derivatives and Gauss weights: y is t1 of
-  // x-faces and t2 of z-faces
+  // faces past the end of a partial tile take part in the row passes (and their
+  // barriers) but store nothing
+  const bool active = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
+  const int tp[3] = {fx, fy, fz};
+  // the stretched y of the channel, when tangential, is the row axis S (it is the
+  // tile's shorter tangential extent); R is never stretched
   const bool ys = CHAN && DIR != 1 && g.stretch_y;
-  T i2m = T(g.inv_h[A2]), i2p = i2m, w2m = T(1), w2p = T(1);
-  if (ys && DIR == 2) {
-    i2m = T(ym_gp_inv(g, gy, 0));
-    i2p = T(ym_gp_inv(g, gy, 1));
-    w2m = T(ym_gp_w(g, gy, 0));
-    w2p = T(ym_gp_w(g, gy, 1));
-  }
+  const T iR = T(g.inv_h[RG::AR]);
   T Fs[5] = {0, 0, 0, 0, 0}, dFs[5] = {0, 0, 0, 0, 0};
+  if constexpr (!kSharedRows<T, DIR>) {
+    if (!active) return;
+    per_face_phase2<T, DIR, STAGE2, VAR_MU>(g, ff, tp, gy, ys, Fs, dFs);
+  } else {
 #pragma unroll 1
-  for (int m = 0; m < 2; ++m) {  // t1 Gauss point (-, +)
-    T i1 = T(g.inv_h[A1]), w1 = T(1);
-    if (ys && DIR == 0) {
-      i1 = T(ym_gp_inv(g, gy, m));
-      w1 = T(ym_gp_w(g, gy, m));
+  for (int pt = 0; pt < 2; ++pt) {  // S Gauss point (-, +)
+    T iS = T(g.inv_h[RG::AS]), wS = T(1);
+    if (ys) {
+      iS = T(ym_gp_inv(g, gy, pt));
+      wS = T(ym_gp_w(g, gy, pt));
     }
     T Qg[2][5], Dg[2][3][5];
-    gp_data<T, DIR>(ff, corner, m, i1, i2m, i2p, Qg, Dg);
 #pragma unroll
-    for (int l = 0; l < 2; ++l) {
-      T F[5], dF[5];
-      smooth_flux<!STAGE2, VAR_MU>(g, Qg[l], Dg[l], F, dF);
-      const T w = ys ? w1 * (l ? w2p : w2m) : T(1);
+    for (int k = 0; k < 5; ++k) {
+      // two row buffers in turn: the rows of the next component are written while
+      // no thread can still be reading the buffer from two components back
+      T* buf = rowbuf + ((pt + k) & 1) * RG::NBUF;
+      rows_pass<T, DIR>(ff, buf, pt, k);
+      __syncthreads();
+      T vR[2], dR[2], dS[2], dn[2];
+      rows_combine<T, DIR>(buf, tp[DIR], tp[RG::AS], tp[RG::AR], vR, dR, dS, dn);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        if (!STAGE2) Fs[k] += ys ? w * F[k] : F[k];
-        dFs[k] += ys ? w * dF[k] : dF[k];
+      for (int l = 0; l < 2; ++l) {
+        Qg[l][k] = vR[l];
+        Dg[l][0][k] = dn[l];
+        Dg[l][RG::SWAP ? 2 : 1][k] = dS[l] * iS;
+        Dg[l][RG::SWAP ? 1 : 2][k] = dR[l] * iR;
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        T F[5], dF[5];
+        smooth_flux<!STAGE2, VAR_MU>(g, Qg[l], Dg[l], F, dF);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          if (!STAGE2) Fs[k] += ys ? wS * F[k] : F[k];
+          dFs[k] += ys ? wS * dF[k] : dF[k];
+        }
       }
     }
   }
+  }
+  if (!active) return;
   // face n+1/2 is stored at cell n; the bottom wall face of the channel (row -1)
   // goes to its own array
   T* out = fl;
@@ -108,7 +174,8 @@ flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const
                   int nty, int ntz, int nper) {
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ff, ntx, nty, ntz, nper);
+  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
 template <typename T, int DIR>
@@ -117,7 +184,8 @@ __global__ void __launch_bounds__(256) flux_fused_varmu_kernel(Geo g, const doub
                                                                int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ff, ntx, nty, ntz, nper);
+  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
 // Channel: walls in y and/or the stretched y mesh (the metric branches are
@@ -130,7 +198,8 @@ flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
                                                               int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  flux_fused_body<T, DIR, STAGE2, VAR_MU, true>(g, q, fl, ff, ntx, nty, ntz, nper);
+  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  flux_fused_body<T, DIR, STAGE2, VAR_MU, true>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
 template <int DIR>

@@ -28,6 +28,7 @@ struct TileGeomB {
   static constexpr int FX = BX + 2 * HX, FY = BY + 2 * HY, FZ = BZ + 2 * HZ;
   static constexpr int NFF = FX * FY * FZ;
   static constexpr int S[3] = {1, FX, FX * FY};  // LDS strides of the face-field tile
+  static constexpr int BA[3] = {BX, BY, BZ};      // faces along each axis
   static_assert(BX * BY * BZ == 256, "one face per thread");
 };
 template <int DIR>
@@ -241,6 +242,82 @@ __device__ __forceinline__ void gp_data(const T* ff, int corner, int m, T i1, T 
     Dg[0][2][k] = d2m * i2m;
     Dg[1][2][k] = d2p * i2p;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2 with shared rows.  The tangential reconstruction at a Gauss point is a
+// tensor product: five-point sums along one tangential axis (S, "rows"), then a
+// five-point combination of five rows along the other (R).  A row sum depends on
+// the face's S position and on the row's R position only, so the faces of the
+// tile that share an S position share their rows: each row is summed once per
+// tile (pass A, into LDS) instead of once per face that uses it (five times).
+// S is the tile's shorter tangential extent, which keeps the R halo (two rows on
+// each side) a small fraction: (B_R + 4) / B_R rows per face.
+// ---------------------------------------------------------------------------
+template <int DIR, class TG = TileGeom<DIR>>
+struct RowGeom {
+  static constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
+  static constexpr bool SWAP = TG::BA[A2] < TG::BA[A1];  // S = t2 when t2 is the shorter axis
+  static constexpr int AS = SWAP ? A2 : A1, AR = SWAP ? A1 : A2;
+  static constexpr int BN = TG::BA[DIR], BS = TG::BA[AS], BR = TG::BA[AR];
+  // row entries: normal position, S position and R row (with its halo of two);
+  // laid out x fastest, as the threads are, so that neighbouring lanes touch
+  // neighbouring words (no LDS bank conflicts)
+  static constexpr int E[3] = {DIR == 0 ? BN : (AS == 0 ? BS : BR + 4), DIR == 1 ? BN : (AS == 1 ? BS : BR + 4),
+                               DIR == 2 ? BN : (AS == 2 ? BS : BR + 4)};
+  static constexpr int ES[3] = {1, E[0], E[0] * E[1]};
+  static constexpr int NE = E[0] * E[1] * E[2];
+  static constexpr int NBUF = 3 * NE;  // value, S-derivative and normal-derivative rows
+};
+
+// Pass A for S Gauss point pt (0: -, 1: +) and component k: the rows of Q0 (value
+// and S-derivative weights) and of dQ0/dn (value weights) into buf[3][NE].
+template <typename T, int DIR, class TG = TileGeom<DIR>>
+__device__ __forceinline__ void rows_pass(const T* ff, T* buf, int pt, int k) {
+  using RG = RowGeom<DIR, TG>;
+  const T* wv = tang_table<T>(pt);
+  const T* wd = wv + 5;
+  constexpr int sS = TG::S[RG::AS];
+  for (int e = threadIdx.x; e < RG::NE; e += 256) {
+    // (normal, S position, R row) in face-field coordinates: the S taps start at
+    // the face's own position (halo of two), the R row is already in halo coordinates
+    const int c0 = e % RG::E[0], c1 = (e / RG::E[0]) % RG::E[1], c2 = e / (RG::E[0] * RG::E[1]);
+    const int base = c0 * TG::S[0] + c1 * TG::S[1] + c2 * TG::S[2];
+    const T* f0 = ff + k * TG::NFF + base;
+    const T* fn = ff + (5 + k) * TG::NFF + base;
+    T v = wv[0] * f0[0], d = wd[0] * f0[0], w = wv[0] * fn[0];
+#pragma unroll
+    for (int a = 1; a < 5; ++a) {
+      const T x = f0[a * sS], y = fn[a * sS];
+      v = v + wv[a] * x;
+      d = d + wd[a] * x;
+      w = w + wv[a] * y;
+    }
+    buf[e] = v;
+    buf[RG::NE + e] = d;
+    buf[2 * RG::NE + e] = w;
+  }
+}
+
+// Pass B for the face at tile position (n, s, rr) (normal, S, R): values and
+// derivatives of component k at the two R Gauss points l = 0 (-), 1 (+) from its
+// five rows.  vR[l] = Q0, dR[l] = dQ0/dR, dS[l] = dQ0/dS (per unit width), dn[l] = dQ0/dn.
+template <typename T, int DIR, class TG = TileGeom<DIR>>
+__device__ __forceinline__ void rows_combine(const T* buf, int n, int s, int rr, T* vR, T* dR, T* dS, T* dn) {
+  using RG = RowGeom<DIR, TG>;
+  const int e0 = n * RG::ES[DIR] + s * RG::ES[RG::AS] + rr * RG::ES[RG::AR];
+  constexpr int st = RG::ES[RG::AR];
+  T rv[5], rd[5], rn[5];
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    rv[b] = buf[e0 + b * st];
+    rd[b] = buf[RG::NE + e0 + b * st];
+    rn[b] = buf[2 * RG::NE + e0 + b * st];
+  }
+  tang_val(rv, vR[0], vR[1]);
+  tang_der(rv, dR[0], dR[1]);
+  tang_val(rd, dS[0], dS[1]);
+  tang_val(rn, dn[0], dn[1]);
 }
 
 }  // namespace hgks
