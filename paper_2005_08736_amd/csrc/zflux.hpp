@@ -32,6 +32,32 @@ __host__ __device__ __forceinline__ T zratio(T tau5, T b, T eps, int p) {
   return out;
 }
 
+// The three ratios (tau5 / (b_k + eps))^p.  In double one division serves all
+// three (1/d0 = d1 d2 / (d0 d1 d2) and so on; the product stays far inside the
+// FP64 range for any b); in float each keeps its own division, because the
+// product of three denominators could leave the FP32 range on a steep line.
+template <typename T>
+__host__ __device__ __forceinline__ void zratios(T tau5, T b0, T b1, T b2, T eps, int p, T& r0, T& r1, T& r2) {
+  if constexpr (sizeof(T) == sizeof(float)) {
+    r0 = zratio(tau5, b0, eps, p);
+    r1 = zratio(tau5, b1, eps, p);
+    r2 = zratio(tau5, b2, eps, p);
+  } else {
+    const T d0 = b0 + eps, d1 = b1 + eps, d2 = b2 + eps;
+    const T d01 = d0 * d1;
+    const T t = tau5 / (d01 * d2);
+    const T x0 = t * (d1 * d2), x1 = t * (d0 * d2), x2 = t * d01;
+    r0 = x0;
+    r1 = x1;
+    r2 = x2;
+    for (int i = 1; i < p; ++i) {
+      r0 = r0 * x0;
+      r1 = r1 * x1;
+      r2 = r2 * x2;
+    }
+  }
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ void zbeta(const T* v, T& b0, T& b1, T& b2) {
   const T c13 = T(13.0 / 12.0);
@@ -49,11 +75,13 @@ __host__ __device__ __forceinline__ void weno_z_right(const T* v, T eps, int p, 
   T b0, b1, b2;
   zbeta(v, b0, b1, b2);
   T tau5 = fabs(b0 - b2);
-  T a0 = T(0.1) * (T(1) + zratio(tau5, b0, eps, p));
-  T a1 = T(0.6) * (T(1) + zratio(tau5, b1, eps, p));
-  T a2 = T(0.3) * (T(1) + zratio(tau5, b2, eps, p));
-  T sum = a0 + a1 + a2;
-  T w0 = a0 / sum, w1 = a1 / sum, w2 = a2 / sum;
+  T r0, r1, r2;
+  zratios(tau5, b0, b1, b2, eps, p, r0, r1, r2);
+  T a0 = T(0.1) * (T(1) + r0);
+  T a1 = T(0.6) * (T(1) + r1);
+  T a2 = T(0.3) * (T(1) + r2);
+  const T isum = T(1) / (a0 + a1 + a2);
+  T w0 = a0 * isum, w1 = a1 * isum, w2 = a2 * isum;
   T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
   T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
   T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
@@ -69,23 +97,24 @@ __host__ __device__ __forceinline__ void weno_z_edges(const T* v, T eps, int p, 
   T b0, b1, b2;
   zbeta(v, b0, b1, b2);
   T tau5 = fabs(b0 - b2);
-  T r0 = zratio(tau5, b0, eps, p), r1 = zratio(tau5, b1, eps, p), r2 = zratio(tau5, b2, eps, p);
+  T r0, r1, r2;
+  zratios(tau5, b0, b1, b2, eps, p, r0, r1, r2);
   {
     T a0 = T(0.1) * (T(1) + r0), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r2);
-    T sum = a0 + a1 + a2;
+    const T isum = T(1) / (a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
-    eb = (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2;
+    eb = (a0 * q0 + a1 * q1 + a2 * q2) * isum;
   }
   {
     // reversed line (v4, v3, v2, v1, v0): indicators (b2, b1, b0)
     T a0 = T(0.1) * (T(1) + r2), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r0);
-    T sum = a0 + a1 + a2;
+    const T isum = T(1) / (a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[4] - T(7.0 / 6.0) * v[3] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[3] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[1];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[1] - T(1.0 / 6.0) * v[0];
-    ea = (a0 / sum) * q0 + (a1 / sum) * q1 + (a2 / sum) * q2;
+    ea = (a0 * q0 + a1 * q1 + a2 * q2) * isum;
   }
 }
 
@@ -270,15 +299,28 @@ __host__ __device__ __forceinline__ void zexpect_phi(const T* A, const ZGauss<T>
 
 // Slope polynomial a with <a psi> = b for a Maxwellian (U, V, W, lambda): the
 // 5 x 5 system of Gaussian moments solved in closed form.
+// The Maxwellian's factors are shared by all solves with it (zslope_coef):
+// Ep = (|U|^2 + (K+3)/(2 lambda))/2 and c4 = 8 lambda^2/(K+3).
 template <typename T>
-__host__ __device__ __forceinline__ void zslope(const T* b, T U, T V, T W, T lam, T K, T* a) {
-  T Ep = T(0.5) * (U * U + V * V + W * W + (K + T(3)) / (T(2) * lam));
+struct ZSlopeCoef {
+  T Ep, c4, tl;  // tl = 2 lambda
+};
+template <typename T>
+__host__ __device__ __forceinline__ ZSlopeCoef<T> zslope_coef(T U, T V, T W, T lam, T i2l, T K) {
+  ZSlopeCoef<T> c;
+  c.Ep = T(0.5) * (U * U + V * V + W * W + (K + T(3)) * i2l);
+  c.c4 = T(8) * lam * lam / (K + T(3));
+  c.tl = T(2) * lam;
+  return c;
+}
+template <typename T>
+__host__ __device__ __forceinline__ void zslope(const T* b, T U, T V, T W, const ZSlopeCoef<T>& c, T* a) {
   T B = b[1] - U * b[0], C = b[2] - V * b[0], D = b[3] - W * b[0];
-  a[4] = T(8) * lam * lam / (K + T(3)) * (b[4] - Ep * b[0] - U * B - V * C - W * D);
-  a[1] = T(2) * lam * B - U * a[4];
-  a[2] = T(2) * lam * C - V * a[4];
-  a[3] = T(2) * lam * D - W * a[4];
-  a[0] = b[0] - U * a[1] - V * a[2] - W * a[3] - Ep * a[4];
+  a[4] = c.c4 * (b[4] - c.Ep * b[0] - U * B - V * C - W * D);
+  a[1] = c.tl * B - U * a[4];
+  a[2] = c.tl * C - V * a[4];
+  a[3] = c.tl * D - W * a[4];
+  a[0] = b[0] - U * a[1] - V * a[2] - W * a[3] - c.Ep * a[4];
 }
 
 // Primitive variables of a local-frame deviation state.
@@ -337,13 +379,14 @@ __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5
   T M[7];
   zmom_gauss(M, 7, s.U, i2l);
   T a[3][5];
+  const ZSlopeCoef<T> sc = zslope_coef(s.U, s.V, s.W, s.lam, i2l, K);
   const T ir = T(1) / s.rho;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T b[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = D[d][k] * ir;
-    zslope(b, s.U, s.V, s.W, s.lam, K, a[d]);
+    zslope(b, s.U, s.V, s.W, sc, a[d]);
   }
   T ea[4][4];
   zexpect_slopes(a, G, ea);
@@ -354,7 +397,7 @@ __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5
     T bt[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) bt[k] = -ra0[k];
-    zslope(bt, s.U, s.V, s.W, s.lam, K, A);
+    zslope(bt, s.U, s.V, s.W, sc, A);
   }
   if (half != 0) {
     zmom_half(M, s.U, s.lam, i2l, T(half));
