@@ -34,7 +34,12 @@ def test_workspace_size_and_validation():
     ws = hgks.workspace_bytes(p)
     assert ws >= 40 * 8 * 32 ** 3
     assert ws % 256 == 0
-    for bad in (dict(nx=5), dict(gamma=1.0), dict(cfl=0.0), dict(prandtl=-1.0), dict(mode=7), dict(mu_ref=-1.0)):
+    # boxes of 2^31 cells and more are rejected: the launch grids count cells in 32 bits
+    big = dict(p)
+    big.update(nx=2048, ny=1024, nz=1023)
+    assert hgks.workspace_bytes(big) >= 360 * 2048 * 1024 * 1023  # 45 doubles per cell besides the state
+    for bad in (dict(nx=5), dict(gamma=1.0), dict(cfl=0.0), dict(prandtl=-1.0), dict(mode=7), dict(mu_ref=-1.0),
+                dict(nx=2048, ny=2048, nz=512)):
         q = dict(p)
         q.update(bad)
         assert hgks.workspace_bytes(q) == 0, bad

@@ -1,0 +1,76 @@
+"""GPU parity on a large box: 1024 x 1024 x 416 cells (4.4e8, about 175 GB of
+device memory with the workspace), where the ten-field face-flux arrays hold
+more than 2^32 values and the five-field state more than 2^31, so every 64-bit
+offset of the kernels is exercised.  The oracle checks dt over the whole box and
+Q^{n+1} at sampled cells (near the high corners too) from windows holding each
+cell's two-stage dependence."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_08736_amd import cases, hgks
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def test_large_box_64bit_offsets_sampled_step():
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    dev = torch.device("cuda:0")
+    nx, ny, nz = 1024, 1024, 416
+    h = 2 * math.pi / nx
+    p = cases.params(nx=nx, ny=ny, nz=nz, lx=nx * h, ly=ny * h, lz=nz * h, mu_ref=1.0 / 1600, prandtl=0.72)
+    announce(f"large box {nx}x{ny}x{nz} ({nx * ny * nz:.3e} cells), workspace "
+             f"{hgks.workspace_bytes(p) / 1e9:.1f} GB")
+    # a smooth periodic field (Taylor-Green-like velocity, varying density and
+    # pressure), built on the device from broadcast 1-D factors
+    x = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * h
+    y = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * h
+    z = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * h * (nx / nz)
+    sx, cx = torch.sin(x)[None, None, :], torch.cos(x)[None, None, :]
+    sy, cy = torch.sin(y)[None, :, None], torch.cos(y)[None, :, None]
+    cz = torch.cos(z)[:, None, None]
+    gamma = p["gamma"]
+    q = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=dev)
+    q[0] = 1.0 + 0.05 * torch.sin(x + 0.3)[None, None, :] * cy * cz
+    q[1] = sx * cy * cz
+    q[2] = -cx * sy * cz
+    q[3] = 0.1 * cx * cy * torch.sin(z)[:, None, None]
+    pr = 71.4 + 0.25 * torch.cos(2 * x)[None, None, :] * torch.cos(2 * y)[None, :, None] * (cz + 2)
+    q[4] = pr / (gamma - 1) + 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2)
+    q[1:4] *= q[0]
+    del pr
+    q0 = q.cpu().numpy()
+    s = hgks.Solver(p, q)
+    dts = s.step(1, return_dt=True)
+    torch.cuda.synchronize()
+    dt_ref = oracle.cfl_dt(p, q0)
+    announce(f"  dt {dts[0]:.15e}  oracle {dt_ref:.15e}")
+    assert abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.default_rng(4416)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))) for _ in range(4)]
+    pts += [(nx - 1, ny - 1, nz - 1), (nx - 3, ny - 1, nz - 2), (0, ny - 2, nz - 1), (5, 7, 0)]
+    for c in pts:
+        ii = np.arange(c[0] - 6, c[0] + 7) % nx
+        jj = np.arange(c[1] - 6, c[1] + 7) % ny
+        kk = np.arange(c[2] - 6, c[2] + 7) % nz
+        win = np.ascontiguousarray(q0[:, kk][:, :, jj][:, :, :, ii])
+        pw = dict(p)
+        pw.update(nx=13, ny=13, nz=13, lx=13 * h, ly=13 * h, lz=13 * h)
+        qw, _ = oracle.step(pw, win, 1, dt=dts[0])
+        got = q[:, c[2], c[1], c[0]].cpu().numpy()
+        ref = qw[:, 6, 6, 6]
+        announce(f"  cell {c}: max abs diff {np.abs(got - ref).max():.2e}")
+        assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(np.abs(ref), 1.0)), (c, got - ref)
+    s.close()
+    del s, q
+    torch.cuda.empty_cache()
