@@ -52,13 +52,15 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   const T K = T(g.K);
   T dum, tok = T(0);
   // values (and t2-derivatives) of Q_l, Q_r and Q0 first: the collision time needs them
+  // (the two Gauss points with the same t1 point split each pair of WENO-Z edge
+  // evaluations between them, zgp_pair)
   T Ql[5], Qr[5], Q0[5], Ql2[5], Qr2[5], Q02[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    zgp_field<T, DIR, false>(g, ff, ed, kZQl + k, a, t, sm, sl, Ql[k], dum, Ql2[k], tok);
-    zgp_field<T, DIR, false>(g, ff, ed, kZQr + k, a, t, sm, sl, Qr[k], dum, Qr2[k], tok);
-    zgp_field<T, DIR, false>(g, ff, ed, kZQ0 + k, a, t, sm, sl, Q0[k], dum, Q02[k], tok);
-  }
+  for (int k = 0; k < 5; ++k)
+    zgp_pair<T, DIR, false>(g, ff, ed, kZQl + k, kZQr + k, a, t, sm, sl, Ql[k], Ql2[k], Qr[k], Qr2[k], tok);
+  zgp_pair<T, DIR, false>(g, ff, ed, kZQ0 + 0, kZQ0 + 1, a, t, sm, sl, Q0[0], Q02[0], Q0[1], Q02[1], tok);
+  zgp_pair<T, DIR, false>(g, ff, ed, kZQ0 + 2, kZQ0 + 3, a, t, sm, sl, Q0[2], Q02[2], Q0[3], Q02[3], tok);
+  zgp_field<T, DIR, false>(g, ff, ed, kZQ0 + 4, a, t, sm, sl, Q0[4], dum, Q02[4], tok);
   ZCoef<T> c;
   zflux_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
   ZAcc<T> acc;
@@ -66,8 +68,7 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
     T D[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      zgp_field<T, DIR, false>(g, ff, ed, kZDn + k, a, t, sm, sl, D[0][k], dum, dum, tok);
-      zgp_field<T, DIR, true>(g, ff, ed, kZQ0 + k, a, t, sm, sl, dum, D[1][k], dum, tok);
+      zgp_pair<T, DIR, true>(g, ff, ed, kZDn + k, kZQ0 + k, a, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
       D[2][k] = Q02[k];
     }
     zside(c.s0, D, 0, K, c.eq1, c.eqh, acc, true);
@@ -79,8 +80,7 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
     T D[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      zgp_field<T, DIR, false>(g, ff, ed, kZDl + k, aa, t, sm, sl, D[0][k], dum, dum, tok);
-      zgp_field<T, DIR, true>(g, ff, ed, kZQl + k, aa, t, sm, sl, dum, D[1][k], dum, tok);
+      zgp_pair<T, DIR, true>(g, ff, ed, kZDl + k, kZQl + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
       D[2][k] = Ql2[k];
     }
     zside(c.sl, D, +1, K, c.in1, c.inh, acc, false);
@@ -91,8 +91,7 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
     T D[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      zgp_field<T, DIR, false>(g, ff, ed, kZDr + k, aa, t, sm, sl, D[0][k], dum, dum, tok);
-      zgp_field<T, DIR, true>(g, ff, ed, kZQr + k, aa, t, sm, sl, dum, D[1][k], dum, tok);
+      zgp_pair<T, DIR, true>(g, ff, ed, kZDr + k, kZQr + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
       D[2][k] = Qr2[k];
     }
     zside(c.sr, D, -1, K, c.in1, c.inh, acc, false);

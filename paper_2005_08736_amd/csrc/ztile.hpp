@@ -126,4 +126,63 @@ __device__ __forceinline__ void zgp_field(const Geo& g, const T* ff, const T* ed
   }
 }
 
+// Phase 3 helper for two reconstructions at once, shared by the two Gauss points
+// of a face with the same t1 point (adjacent lanes, sl = -1 and +1): the WENO-Z
+// edge pair across the five lines does not depend on sl, so the lane with
+// sl = -1 evaluates it for job A, the lane with sl = +1 for job B, and the two
+// exchange their edges.  Job A is the value rows of field fA (value and
+// t2-derivative out); job B the value rows of field fB (DB = false: value and
+// t2-derivative out) or its t1-derivative rows (DB = true: t1-derivative out in
+// outB).  Every lane of the workgroup must take part.
+template <typename T, int DIR, bool DB>
+__device__ __forceinline__ void zgp_pair(const Geo& g, const T* ff, const T* ed, int fA, int fB, int a, int t, T sm,
+                                         T sl, T& valA, T& d2A, T& outB, T& outB2, T& token) {
+  using TG = ZTileGeom<DIR>;
+  const T eps = T(g.weno_eps);
+  zdep(a, token);
+  const bool mineB = sl > T(0);
+  const int f = mineB ? fB : fA;
+  // rows as c_m m + c_d (eb - ea) + c_s (ea + eb - 2 m): value rows (1, sm G, 0),
+  // t1-derivative rows (0, 1, sm sqrt 3)
+  const bool der = DB && mineB;
+  const T c_m = der ? T(0) : T(1);
+  const T c_d = der ? T(1) : sm * T(kGauss);
+  const T c_s = der ? sm * T(kS3) : T(0);
+  T row[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const T m = ff[f * TG::NFF + (t + r) * TG::P + a + 2];
+    const int li = f * TG::NROW + (t + r) * TG::B + a;
+    const T ea = ed[2 * li], eb = ed[2 * li + 1];
+    row[r] = c_m * m + c_d * (eb - ea) + c_s * (ea + eb - T(2) * m);
+  }
+  T ea, eb;
+  weno_z_edges(row, eps, g.weno_p, ea, eb);
+  const T pa = __shfl_xor(ea, 1), pb = __shfl_xor(eb, 1);
+  const T eaA = mineB ? pa : ea, ebA = mineB ? pb : eb;
+  const T eaB = mineB ? ea : pa, ebB = mineB ? eb : pb;
+  // middle rows of both jobs
+  T midA, midB;
+  {
+    const T m = ff[fA * TG::NFF + (t + 2) * TG::P + a + 2];
+    const int li = fA * TG::NROW + (t + 2) * TG::B + a;
+    midA = zpar_val(m, ed[2 * li], ed[2 * li + 1], sm);
+  }
+  {
+    const T m = ff[fB * TG::NFF + (t + 2) * TG::P + a + 2];
+    const int li = fB * TG::NROW + (t + 2) * TG::B + a;
+    midB = DB ? zpar_der(m, ed[2 * li], ed[2 * li + 1], sm) : zpar_val(m, ed[2 * li], ed[2 * li + 1], sm);
+  }
+  valA = zpar_val(midA, eaA, ebA, sl);
+  d2A = zpar_der(midA, eaA, ebA, sl) * T(g.inv_h[TG::A2]);
+  if (DB) {
+    outB = zpar_val(midB, eaB, ebB, sl) * T(g.inv_h[TG::A1]);
+    outB2 = T(0);
+  } else {
+    outB = zpar_val(midB, eaB, ebB, sl);
+    outB2 = zpar_der(midB, eaB, ebB, sl) * T(g.inv_h[TG::A2]);
+  }
+  token = outB;
+}
+
 }  // namespace hgks
