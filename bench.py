@@ -117,6 +117,75 @@ def adjoint_timing(r, reps, torch, label):
     return out
 
 
+def adjoint_tgv128_timing(torch, cases, hgks, dev):
+    """The adjoint workload itself: gradient of E_k after 100 steps of the 128^3
+    Taylor-Green run (plus the seeded 1% solenoidal perturbation) with respect to
+    the initial state, checkpoint every 10 steps with recompute, dt frozen from
+    the forward run; its wall time against the 100 forward steps alone."""
+    from paper_2005_08736_amd import autograd as ag
+    n, steps = 128, 100
+    p = cases.tgv_params(n)
+    q = cases.tgv_state(n)
+    U = q[1:4] / q[0] + cases.solenoidal_perturbation(n, seed=0, kmax=4.0, rms=0.01)
+    q[4] += 0.5 * q[0] * ((U ** 2).sum(axis=0)) - 0.5 * (q[1:4] ** 2).sum(axis=0) / q[0]
+    q[1:4] = q[0] * U
+    q0 = torch.from_numpy(q).to(dev)
+    dts = ag.cfl_time_steps(p, q0, steps)
+    st = ag.Stepper(p, q0)
+
+    def energy(x):
+        return 0.5 * torch.sum((x[1] ** 2 + x[2] ** 2 + x[3] ** 2) / x[0]) / x[0].numel()
+
+    # the forward run as the library does it: 100 CFL steps in one call (the same
+    # time steps that were frozen above)
+    work = q0.clone()
+    fwd = hgks.Solver(p, work)
+    fwd.step(2)
+    work.copy_(q0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    e_fwd = energy(work).item()
+    fwd.close()
+    t0 = time.perf_counter()
+    qg = q0.clone().requires_grad_(True)
+    J = energy(ag.run_checkpointed(st, qg, dts, every=10))
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    if not bool(torch.isfinite(qg.grad).all()) or abs(J.item() - e_fwd) > 1e-12 * abs(e_fwd):
+        raise RuntimeError("adjoint workload: non-finite gradient or a forward pass that differs")
+    out = {"workload": "Taylor-Green 128^3 + 1% solenoidal perturbation, dE_k(step 100)/dQ0, checkpoint every 10",
+           "s_forward_100_steps": t_fwd, "s_gradient": t_grad, "ratio_gradient_vs_forward": t_grad / t_fwd,
+           "note": "gradient = forward pass, then per segment a recompute and the step adjoints, one call per step"}
+    log(f"[bench] adjoint workload 128^3 x 100 steps: forward {t_fwd:.3f} s, gradient with checkpointing "
+        f"{t_grad:.3f} s, ratio {t_grad / t_fwd:.2f}")
+    return out
+
+
+def adjoint_modez_timing(reps, torch, cases, hgks, dev):
+    """The mode-Z adjoint on its checked workload: Taylor-Green 32^3 in mode Z
+    (WENO-Z weights and full flux), FP64; forward step time and step-adjoint
+    time at the state after 5 CFL steps."""
+    n = 32
+    p = cases.tgv_params(n, mode=hgks.MODE_WENOZ)
+    q = torch.from_numpy(cases.tgv_state(n)).to(dev)
+    s = hgks.Solver(p, q)
+    dts = s.step(5, return_dt=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(10, dt=float(dts[-1]))
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t0) / 10 * 1e3
+    r = {"solver": s, "q": q, "dts": dts, "ms": ms_fwd}
+    out = adjoint_timing(r, reps, torch, "mode Z, Taylor-Green 32^3, FP64")
+    out["ms_per_forward_step"] = ms_fwd
+    s.close()
+    return out
+
+
 def other_workloads(args, torch, np, cases, hgks, dev):
     """Throughput of the paper's other two workloads, each in its own solver:
     decaying isotropic turbulence at 256^3 (WENO-Z + full flux, mu ~ T^0.76,
@@ -226,6 +295,8 @@ def main():
     adj = adjoint_timing(r64, args.adjoint_reps, torch, "FP64")
     r32 = run(hgks.PREC_F32FLUX)
     adj["fp32_form"] = adjoint_timing(r32, args.adjoint_reps, torch, "FP32-flux form")
+    adj["mode_z_32"] = adjoint_modez_timing(args.adjoint_reps, torch, cases, hgks, dev)
+    adj["tgv128_gradient"] = adjoint_tgv128_timing(torch, cases, hgks, dev)
     others = other_workloads(args, torch, np, cases, hgks, dev) if args.other_steps > 0 else None
     value = r64["value"]
     ms_per_step = r64["ms"]
