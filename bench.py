@@ -354,6 +354,10 @@ def main():
         "adjoint": adj,
         "other_workloads": others,
         "cpu_baseline": cpu,
+        "paper_context": {"value": PAPER_MCUPS_256, "unit": UNIT, "workload": "Taylor-Green 256^3, FP64 (presumed)",
+                          "hardware": "64 cores, Intel Xeon E5-2692 2.2 GHz (TianHe-II), MPI",
+                          "source": "Sec. 3.2, Table time_table1: 9.09 s per step",
+                          "note": "another machine's figure: context, not the target"},
     }
     print(json.dumps(out), flush=True)
 
