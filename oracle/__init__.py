@@ -51,6 +51,7 @@ def lib():
             "hgks_ref_diagnostics": (i32, [P, _D, _D]),
             "hgks_ref_ndiag": (i32, []),
             "hgks_ref_jvp": (i32, [P, _D, _D, i32, _D, _D, _D]),
+            "hgks_ref_count_face_flux": (i32, [P, _D, i32, dbl, _D]),
             "hgks_ref_moments_1d": (i32, [dbl, dbl, _D, _D]),
             "hgks_ref_psimom": (i32, [dbl, dbl, dbl, dbl, dbl, i32, i32, i32, i32, _D, _D]),
             "hgks_ref_microslope": (i32, [_D, dbl, dbl, dbl, dbl, dbl, _D]),
@@ -134,6 +135,21 @@ def face_flux(params: dict, q: np.ndarray, direction: int, dt: float = 0.0):
     rc = lib().hgks_ref_face_flux(ctypes.byref(make_params(params)), _p(q), int(direction), float(dt), _p(F), _p(dF))
     _check(rc, "face_flux")
     return F, dF
+
+
+COUNT_KINDS = ["add", "sub", "mul", "div", "sqrt", "exp", "erfc", "pow"]
+
+
+def count_face_flux(params: dict, q: np.ndarray, direction: int, dt: float = 0.0) -> dict:
+    """Operation counts of the oracle's face fluxes of one direction, per face
+    (the algorithm as the oracle writes it, run on a counting scalar)."""
+    q = _arr(q)
+    out = np.zeros(len(COUNT_KINDS))
+    rc = lib().hgks_ref_count_face_flux(ctypes.byref(make_params(params)), _p(q), int(direction), float(dt),
+                                        _p(out))
+    _check(rc, "count_face_flux")
+    nf = params["nx"] * params["ny"] * params["nz"]
+    return {k: v / nf for k, v in zip(COUNT_KINDS, out)}
 
 
 NDIAG = 34

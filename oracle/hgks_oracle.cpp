@@ -60,6 +60,7 @@
 #include <cstring>
 #include <vector>
 
+#include "counting.hpp"
 #include "dual.hpp"
 
 #ifdef _OPENMP
@@ -1252,6 +1253,29 @@ int hgks_ref_jvp(const ref_params* p, const double* q, const double* dq, int nst
         }
   for (int s = 0; s < nsteps; ++s) ref::step(b, ref::Dual(dts[s]));
   ref::store_deriv(b, q_out, dq_out);
+  return 0;
+}
+
+// Operation counts of the face fluxes of direction dir at state q (Sec. 2 as the
+// oracle writes it: normal reconstruction, compatibility state, tangential
+// reconstruction, Gauss-point flux, face average): counts[8] receives the numbers
+// of +, -, x, /, sqrt, exp, erfc and pow summed over the nx*ny*nz faces.
+int hgks_ref_count_face_flux(const ref_params* p, const double* q, int dir, double dt, double* counts) {
+  if (ref::validate(p) || dir < 0 || dir > 2 || !counts) return -1;
+  ref::Box<ref::Counted> b(*p);
+  for (int c = 0; c < 5; ++c)
+    for (int k = 0; k < b.n[2]; ++k)
+      for (int j = 0; j < b.n[1]; ++j)
+        for (int i = 0; i < b.n[0]; ++i) {
+          size_t o = ((size_t(c) * b.n[2] + k) * b.n[1] + j) * b.n[0] + i;
+          b.at(c, i, j, k) = ref::Counted(q[o]);
+        }
+  ref::fill_ghosts(b);
+  const size_t np = size_t(5) * b.pn[0] * b.pn[1] * b.pn[2];
+  std::vector<ref::Counted> Fn(np, ref::Counted(0.0)), dFn(np, ref::Counted(0.0));
+  ref::reset_counts();
+  ref::face_fluxes(b, dir, ref::Counted(dt), Fn, dFn);
+  for (int k = 0; k < ref::kCntKinds; ++k) counts[k] = double(ref::op_counters()[k].load());
   return 0;
 }
 

@@ -277,3 +277,25 @@ def test_channel_mesh_matches_table():
         assert abs(dy.max() * scale - g["dy_plus_max"][i]) < 0.015
         assert abs(2 * math.pi / n * scale - g["dx_plus"][i]) < 0.015
         assert abs(math.pi / n * scale - g["dz_plus"][i]) < 0.006
+
+
+def test_operation_counts_of_the_face_flux(oracle_mod):
+    """The counting scalar run through the oracle's face fluxes.  The scheme has
+    no data-dependent branches, so the counts are the same for any state and any
+    direction on a cube.  The oracle evaluates the face field once per entry of
+    its padded grid, (n+1) faces along the normal times (n+4)^2 with the
+    tangential halo, and the compatibility state there takes one erfc and one exp
+    per side: 2 (n+1)(n+4)^2 of each in mode S, where nothing else needs them
+    (the Gauss-point flux uses full-space moments only) and no pow appears."""
+    for n in (8, 12):
+        p = cases.tgv_params(n)
+        ref = None
+        for q in (cases.tgv_state(n), cases.uniform_state(n, n, n, rho=1.1, vel=(0.2, 0.1, -0.3), p=0.9)):
+            for d in range(3):
+                c = oracle_mod.count_face_flux(p, q, d, 1e-3)
+                if ref is None:
+                    ref = c
+                assert c == ref, (n, d, c, ref)
+        entries = 2 * (n + 1) * (n + 4) ** 2
+        assert ref["erfc"] * n ** 3 == entries and ref["exp"] * n ** 3 == entries, (n, ref)
+        assert ref["pow"] == 0
