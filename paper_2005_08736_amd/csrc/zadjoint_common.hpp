@@ -12,7 +12,11 @@
 namespace hgks {
 
 // Tangent columns per pass through the Gauss-point flux.
-constexpr int kZTan = 4;
+#ifndef HGKS_ZTAN
+#define HGKS_ZTAN 1
+#endif
+constexpr int kZTan = HGKS_ZTAN;
+static_assert(60 % kZTan == 0, "the passes cover the 60 inputs");
 // Inputs of the Gauss-point flux, local frame: Q0, Q_l, Q_r (values), then the
 // derivatives D0, D_l, D_r, each [3][5] along (n, t1, t2).
 constexpr int kXQ0 = 0, kXQl = 5, kXQr = 10, kXD0 = 15, kXDl = 30, kXDr = 45, kXN = 60;
