@@ -16,7 +16,7 @@ namespace hgks {
 #define HGKS_ZTAN 1
 #endif
 constexpr int kZTan = HGKS_ZTAN;
-static_assert(60 % kZTan == 0, "the passes cover the 60 inputs");
+static_assert(15 % kZTan == 0, "the passes cover the 15 value inputs");
 // Inputs of the Gauss-point flux, local frame: Q0, Q_l, Q_r (values), then the
 // derivatives D0, D_l, D_r, each [3][5] along (n, t1, t2).
 constexpr int kXQ0 = 0, kXQl = 5, kXQr = 10, kXD0 = 15, kXDl = 30, kXDr = 45, kXN = 60;
@@ -55,6 +55,48 @@ __host__ __device__ __forceinline__ void zflux_jt_columns(const Geo& g, const do
     for (int k = 0; k < 5; ++k) s += Fb[k] * F[k].d[j] + dFb[k] * dF[k].d[j];
     Xb[c0 + j] = s;
   }
+}
+
+// The 45 slope columns of J^T (Fb, dFb).  With the three Maxwellians fixed by the
+// values, each side's contribution is linear in its own slopes D (15 of them) and
+// the end formulas are linear in the accumulated moments, so a column is the
+// linear part evaluated on a unit slope: plain double arithmetic, no tangents.
+template <bool VAR_MU>
+__host__ __device__ __forceinline__ void zflux_jt_slopes(const Geo& g, const double* X, double dt, const double* Fb,
+                                                         const double* dFb, double* Xb) {
+  ZCoef<double> c;
+  zflux_begin<VAR_MU>(g, X + kXQ0, X + kXQl, X + kXQr, dt, c);
+  const double K = g.K;
+#pragma unroll 1
+  for (int side = 0; side < 3; ++side) {
+    const ZPrim<double>& s = side == 0 ? c.s0 : (side == 1 ? c.sl : c.sr);
+    const double* k1 = side == 0 ? c.eq1 : c.in1;
+    const double* kh = side == 0 ? c.eqh : c.inh;
+    const int half = side == 0 ? 0 : (side == 1 ? +1 : -1);
+    const int base = side == 0 ? kXD0 : (side == 1 ? kXDl : kXDr);
+#pragma unroll 1
+    for (int i = 0; i < 15; ++i) {
+      double D[3][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+      D[i / 5][i % 5] = 1.0;
+      ZAcc<double> acc;
+      zside<true>(s, D, half, K, k1, kh, acc, true);
+      double F[5], dF[5];
+      zflux_end<true>(g, c, acc, dt, F, dF);
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) sum += Fb[k] * F[k] + dFb[k] * dF[k];
+      Xb[base + i] = sum;
+    }
+  }
+}
+
+// All 60 entries of J^T (Fb, dFb): tangent passes for the 15 values, the linear
+// side maps for the 45 slopes.
+template <bool VAR_MU>
+__host__ __device__ __forceinline__ void zflux_jt_all(const Geo& g, const double* X, double dt, const double* Fb,
+                                                      const double* dFb, double* Xb) {
+  for (int c0 = 0; c0 < kXD0; c0 += kZTan) zflux_jt_columns<VAR_MU>(g, X, c0, dt, Fb, dFb, Xb);
+  zflux_jt_slopes<VAR_MU>(g, X, dt, Fb, dFb, Xb);
 }
 
 // Jacobian of the WENO-Z edge pair of a five-value line:

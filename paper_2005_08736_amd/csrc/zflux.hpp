@@ -367,7 +367,9 @@ struct ZAcc {
 // Adds rho (c0 <u^p psi> + c1 <u^p (a.u) psi> + c2 <u^p A psi>) for p = 1 (I)
 // and p = 0 (J) with the coefficient sets k1 (delta = dt) and kh (dt/2); the
 // time slope A solves <a.u + A> = 0 over the side's full-space Maxwellian.
-template <typename T>
+// With LIN the term of <psi> (the one part that does not scale with D) is left
+// out: the side's contribution is then linear in D.
+template <bool LIN = false, typename T>
 __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* k1,
                                                const T* kh, ZAcc<T>& acc, bool first) {
   const T i2l = T(0.5) / s.lam;
@@ -410,9 +412,14 @@ __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5
   T rA0[5], rA1[5];
   zrows<3, true>(M, eA, rA0, rA1);
   // phi = 1: C_0 = 1
-  T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
   T r10[5], r11[5];
-  zrows<1, true>(M, e1, r10, r11);
+  if (LIN) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r10[k] = r11[k] = T(0);
+  } else {
+    T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
+    zrows<1, true>(M, e1, r10, r11);
+  }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     T j1 = s.rho * (k1[0] * r10[k] + k1[1] * ra0[k] + k1[2] * rA0[k]);
@@ -478,7 +485,9 @@ __host__ __device__ __forceinline__ void zflux_begin_tau(const Geo& g, const T* 
   ztime(T(0.5) * dt, tau, c.eqh, c.inh);
 }
 
-template <typename T>
+// With LIN (acc linear in the slopes, zside<true>) the constant p_ref is not
+// taken out of the normal-momentum flux: F and dF stay linear in acc.
+template <bool LIN = false, typename T>
 __host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>& c, ZAcc<T>& acc, T dt, T* F, T* dF) {
   const T fix = T(g.pr_fix);
   acc.I1[4] = acc.I1[4] + fix * zheat(acc.I1, acc.J1, c.s0.U, c.s0.V, c.s0.W);
@@ -489,7 +498,7 @@ __host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>&
     F[k] = (T(4) * acc.Ih[k] - acc.I1[k]) * idt;
     dF[k] = T(4) * (acc.I1[k] - T(2) * acc.Ih[k]) * idt * idt;
   }
-  F[1] = F[1] - T(g.p_ref);
+  if (!LIN) F[1] = F[1] - T(g.p_ref);
 }
 
 // Full flux with a given collision time (host checks of the device math).

@@ -152,6 +152,17 @@ int dm_zflux_jt(const double* X, double dt, double gamma, double prandtl, double
   return 0;
 }
 
+// The same through the kernel's split: tangents for the values, the linear side
+// maps for the slopes
+int dm_zflux_jt_split(const double* X, double dt, double gamma, double prandtl, double mu, double T_ref,
+                      double mu_exp, double c_art, double rho_ref, double p_ref, const double* Fb, const double* dFb,
+                      double* Xb) {
+  Geo g = make_z(gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref);
+  if (mu_exp != 0.0) zflux_jt_all<true>(g, X, dt, Fb, dFb, Xb);
+  else zflux_jt_all<false>(g, X, dt, Fb, dFb, Xb);
+  return 0;
+}
+
 // Jacobians of the WENO-Z edge pair (J[2][5]) and of the right-edge value and
 // slope (Jv[5], Js[5]) of a five-value line
 int dm_wze_jac(const double* v, double eps, int p, double* J) {

@@ -109,6 +109,14 @@ def zflux_jt(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb
     return Xb
 
 
+def zflux_jt_split(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb, dFb):
+    X, Fb, dFb = _a(X, 60), _a(Fb, 5), _a(dFb, 5)
+    Xb = np.zeros(60)
+    lib().dm_zflux_jt_split(_p(X), *_zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref), _p(Fb),
+                            _p(dFb), _p(Xb))
+    return Xb
+
+
 def wze_jac(v, eps, p):
     v = _a(v, 5)
     J = np.zeros((2, 5))

@@ -176,6 +176,10 @@ def test_zflux_jacobian_transpose_matches_central_differences(p_level, mu_exp):
         Fb, dFb = rng.normal(size=5), rng.normal(size=5)
         args = (dt, GAMMA, 0.72, mu, 1.0, mu_exp, c_art, rho_ref, p_ref)
         Xb = devmath.zflux_jt(X, *args, Fb, dFb)
+        # the kernel's split (tangents for the values, linear side maps for the
+        # slopes) gives the same transpose
+        Xs = devmath.zflux_jt_split(X, *args, Fb, dFb)
+        assert np.abs(Xs - Xb).max() <= 1e-12 * np.abs(Xb).max(), np.abs(Xs - Xb).max()
 
         def f(x):
             F, dF = devmath.zgp_flux(x, *args)
