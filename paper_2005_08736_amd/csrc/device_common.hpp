@@ -128,6 +128,25 @@ __host__ __device__ __forceinline__ void zdep(T& x, const U& after) {
 #endif
 }
 
+// 1/a without the scaling steps of IEEE division, for a whose reciprocal is a
+// normal number (densities, sound speeds).  FP64: the hardware estimate refined
+// by two Newton steps r <- r + r (1 - a r), within about an ulp of the rounded
+// quotient; FP32: the hardware estimate (1 ulp).
+template <typename T>
+__host__ __device__ __forceinline__ T recip(T a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(T) == sizeof(double)) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return fma(r, fma(-a, r, 1.0), r);
+  } else {
+    return __builtin_amdgcn_rcpf(a);
+  }
+#else
+  return T(1) / a;
+#endif
+}
+
 __host__ __device__ __forceinline__ int wrapi(int i, int n) {
   i = i < 0 ? i + n : i;
   return i >= n ? i - n : i;
@@ -200,20 +219,19 @@ struct Side {
 
 template <typename T>
 __host__ __device__ __forceinline__ Side<T> side_state(const Geo& g, const T* dQ) {
-  const T kInvSqrtPi = T(0.56418958354775628695);
   Side<T> s;
   s.rho = T(g.rho_ref) + dQ[0];
-  T ir = T(1) / s.rho;
+  T ir = recip(s.rho);
   s.U = dQ[1] * ir;
   s.V = dQ[2] * ir;
   s.W = dQ[3] * ir;
   s.dp = T(g.gm1) * (dQ[4] - T(0.5) * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
   s.p = T(g.p_ref) + s.dp;
-  T lam = T(0.5) * s.rho / s.p;
-  T sl = sqrt(lam);
-  T x = sl * s.U;
+  // c = 1/sqrt(lambda) = sqrt(2 p / rho): x = U / c, th = c exp(-x^2) / (2 sqrt(pi))
+  T c = sqrt(T(2) * s.p * ir);
+  T x = s.U * recip(c);
   s.h = T(0.5) * erf(x);
-  s.th = T(0.5) * kInvSqrtPi * exp(-x * x) / sl;
+  s.th = T(0.28209479177387814347) * exp(-x * x) * c;
   return s;
 }
 
@@ -259,7 +277,7 @@ template <bool NEED_F, bool VAR_MU, typename T>
 __host__ __device__ __forceinline__ void smooth_flux(const Geo& g, const T* dQ, const T (*D)[5], T* F, T* dF) {
   const T gm1 = T(g.gm1);
   T rho = T(g.rho_ref) + dQ[0];
-  T ir = T(1) / rho;
+  T ir = recip(rho);
   T U0 = dQ[1] * ir, U1 = dQ[2] * ir, U2 = dQ[3] * ir;
   T ke = T(0.5) * (U0 * U0 + U1 * U1 + U2 * U2);
   T dp = gm1 * (dQ[4] - rho * ke);

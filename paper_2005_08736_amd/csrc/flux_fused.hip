@@ -67,7 +67,7 @@ __device__ __forceinline__ void per_face_phase2(const Geo& g, const T* ff, const
   }
 }
 
-template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN>
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN, bool OFF32>
 __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                                 T* ff, T* rowbuf, int ntx, int nty, int ntz, int nper) {
   using TG = TileGeom<DIR>;
@@ -81,7 +81,7 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   double dn_scale = g.inv_h[DIR];
   if (CHAN && DIR == 1 && g.stretch_y) dn_scale = ym_face_inv(g, y0 + 1);
 
-  face_field_tile<T, DIR, CHAN>(g, q, ff, x0, y0, z0, dn_scale);
+  face_field_tile<T, DIR, CHAN, TileGeom<DIR>, OFF32>(g, q, ff, x0, y0, z0, dn_scale);
   __syncthreads();
 
   const int tid = threadIdx.x;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
 #define HGKS_FLUX_WAVES_F32 4
 #endif
 
-template <typename T, int DIR, bool STAGE2>
+template <typename T, int DIR, bool STAGE2, bool OFF32>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_FLUX_WAVES : HGKS_FLUX_WAVES_F32)))
 flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop, int ntx,
@@ -175,17 +175,17 @@ flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
   __shared__ T rowbuf[kRowBuf<T, DIR>];
-  flux_fused_body<T, DIR, STAGE2, false, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
+  flux_fused_body<T, DIR, STAGE2, false, false, OFF32>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
-template <typename T, int DIR>
+template <typename T, int DIR, bool OFF32>
 __global__ void __launch_bounds__(256) flux_fused_varmu_kernel(Geo g, const double* __restrict__ q,
                                                                T* __restrict__ fl, const int* __restrict__ stop,
                                                                int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
   __shared__ T rowbuf[kRowBuf<T, DIR>];
-  flux_fused_body<T, DIR, false, true, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
+  flux_fused_body<T, DIR, false, true, false, OFF32>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
 // Channel: walls in y and/or the stretched y mesh (the metric branches are
@@ -199,7 +199,7 @@ flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
   if (*stop) return;
   __shared__ T ff[10 * TileGeom<DIR>::NFF];
   __shared__ T rowbuf[kRowBuf<T, DIR>];
-  flux_fused_body<T, DIR, STAGE2, VAR_MU, true>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
+  flux_fused_body<T, DIR, STAGE2, VAR_MU, true, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
 template <int DIR>
@@ -215,6 +215,9 @@ template void tile_grid<0>(const Geo&, int&, int&, int&, int&);
 template void tile_grid<1>(const Geo&, int&, int&, int&, int&);
 template void tile_grid<2>(const Geo&, int&, int&, int&, int&);
 
+// Boxes of up to 2^29 cells address every field with 32-bit byte offsets.
+constexpr long long kOff32MaxCells = 1LL << 29;
+
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
 static void launch_dir(const Geo& g, const double* q, T* fl, const int* stop, hipStream_t st) {
   int ntx, nty, ntz, nper;
@@ -222,10 +225,20 @@ static void launch_dir(const Geo& g, const double* q, T* fl, const int* stop, hi
   if (g.wall_y || g.stretch_y)
     flux_fused_chan_kernel<T, DIR, STAGE2, VAR_MU><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx,
                                                                                                   nty, ntz, nper);
-  else if (VAR_MU)
-    flux_fused_varmu_kernel<T, DIR><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty, ntz, nper);
-  else
-    flux_fused_kernel<T, DIR, STAGE2><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty, ntz, nper);
+  else if (g.N <= kOff32MaxCells) {
+    if (VAR_MU)
+      flux_fused_varmu_kernel<T, DIR, true><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
+                                                                                           ntz, nper);
+    else
+      flux_fused_kernel<T, DIR, STAGE2, true><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
+                                                                                             ntz, nper);
+  } else if (VAR_MU) {
+    flux_fused_varmu_kernel<T, DIR, false><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
+                                                                                          ntz, nper);
+  } else {
+    flux_fused_kernel<T, DIR, STAGE2, false><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx, nty,
+                                                                                            ntz, nper);
+  }
 }
 
 template <typename T, bool STAGE2, bool VAR_MU>

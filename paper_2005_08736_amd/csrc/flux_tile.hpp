@@ -75,19 +75,54 @@ __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz,
   }
 }
 
+// Periodic coordinate c >= -n wrapped into [0, n): one conditional add or
+// subtract when c < 2 n (every tile on an axis at least as long as the tile and
+// its halo), the remainder otherwise.
+__device__ __forceinline__ int wrap_coord(int c, int n) {
+  c = c < 0 ? c + n : c;
+  if (c >= n) {
+    c -= n;
+    if (c >= n) c = c % n;
+  }
+  return c;
+}
+
 // Cell averages along the normal of face-field entry e (six cells n-2 .. n+3),
 // as deviations from the reference state, in the local frame; the global cell
 // offsets of the six cells are returned in off.  Periodic axes wrap; with WALL,
 // y is not periodic and rows outside [0, ny) are wall ghosts (their offsets are
-// those of the mirror cells).
-template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>>
+// those of the mirror cells).  OFF32 (for N <= 2^29 cells, where every byte
+// offset into a field fits 32 bits) forms one 32-bit byte offset per cell and
+// adds it to each field's base in the load itself, instead of one 64-bit
+// address per load.
+template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>, bool OFF32 = false>
 __device__ __forceinline__ void normal_stencil(const Geo& g, const double* __restrict__ q, int e, int x0, int y0,
                                                int z0, T (*v)[6], long long* off) {
   const int ex = e % TG::FX, ey = (e / TG::FX) % TG::FY, ez = e / (TG::FX * TG::FY);
   if (!WALL) {
-    int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), wrapmod(y0 + ey - TG::HY, g.n[1]),
-                wrapmod(z0 + ez - TG::HZ, g.n[2])};
+    int c[3] = {wrap_coord(x0 + ex - TG::HX, g.n[0]), wrap_coord(y0 + ey - TG::HY, g.n[1]),
+                wrap_coord(z0 + ez - TG::HZ, g.n[2])};
     const int nn = c[DIR], Nn = g.n[DIR];
+    if (OFF32) {
+      const unsigned sn = unsigned(g.stride[DIR]);
+      const unsigned base = unsigned(c[0]) + unsigned(c[1]) * unsigned(g.stride[1]) +
+                            unsigned(c[2]) * unsigned(g.stride[2]) - unsigned(nn) * sn;
+      unsigned boff[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const unsigned o = base + unsigned(wrapi(nn - 2 + m, Nn)) * sn;
+        off[m] = (long long)o;
+        boff[m] = o * 8u;
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const char* f = (const char*)(q + (long long)gcomp_local<DIR>(k) * g.N);
+        const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v[k][m] = T(*(const double*)(f + boff[m]) - ref);
+      }
+      return;
+    }
     const long long sn = g.stride[DIR];
     const long long base = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] -
                            (long long)nn * sn;
@@ -102,7 +137,7 @@ __device__ __forceinline__ void normal_stencil(const Geo& g, const double* __res
     }
   } else {
     // x and z periodic, y unwrapped (ghost rows allowed)
-    int c[3] = {wrapmod(x0 + ex - TG::HX, g.n[0]), y0 + ey - TG::HY, wrapmod(z0 + ez - TG::HZ, g.n[2])};
+    int c[3] = {wrap_coord(x0 + ex - TG::HX, g.n[0]), y0 + ey - TG::HY, wrap_coord(z0 + ez - TG::HZ, g.n[2])};
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       int cc[3] = {c[0], c[1], c[2]};
@@ -135,14 +170,14 @@ __host__ __device__ __forceinline__ void normal_recon(const T* v, T ih12, T& ql,
 // tangential halo into ff[10][NFF].  dn_scale is 1/h of the normal axis (for
 // y-faces of a stretched mesh, 1/(y' h) at the tile's face row).  The caller
 // synchronizes.
-template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>>
+template <typename T, int DIR, bool WALL = false, class TG = TileGeom<DIR>, bool OFF32 = false>
 __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __restrict__ q, T* ff, int x0, int y0,
                                                 int z0, double dn_scale) {
   const T ih12 = T(dn_scale * (1.0 / 12.0));
   for (int e = threadIdx.x; e < TG::NFF; e += 256) {
     T v[5][6];
     long long off[6];
-    normal_stencil<T, DIR, WALL, TG>(g, q, e, x0, y0, z0, v, off);
+    normal_stencil<T, DIR, WALL, TG, OFF32>(g, q, e, x0, y0, z0, v, off);
     T Ql[5], Qr[5], Dn[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) normal_recon(v[k], ih12, Ql[k], Qr[k], Dn[k]);
