@@ -19,28 +19,37 @@
 
 namespace hgks {
 
-// Phase 2 with rows shared across the tile (rows_pass / rows_combine) or, where
-// the row buffers would cost occupancy, per face (gp_data): the FP64 x-face tile
-// (4 x 8 x 8 with a 12 x 12 halo) already fills 46 KB of LDS, and 18 KB more of
-// rows drops it from three workgroups per CU to two (measured 19% slower).
-#ifndef HGKS_SHARED_ROWS_X64
-#define HGKS_SHARED_ROWS_X64 0
-#endif
-#ifndef HGKS_SHARED_ROWS_X32
-#define HGKS_SHARED_ROWS_X32 1
-#endif
-template <typename T, int DIR>
-constexpr bool kSharedRows = DIR != 0 || (sizeof(T) == 4 ? HGKS_SHARED_ROWS_X32 : HGKS_SHARED_ROWS_X64);
-template <typename T, int DIR>
-constexpr int kRowBuf = kSharedRows<T, DIR> ? 2 * RowGeom<DIR>::NBUF : 1;
+// Tile shapes.  y- and z-faces use TileGeom (32 x 8 along x and the other
+// tangential axis).  x-faces of the periodic kernels use a 2 x 16 x 8 tile whose
+// phase 1 is staged through LDS (face_field_tile_x_staged) and whose phase 2
+// shares rows: its face field (38 KB in FP64) and two row buffers (15 KB, which
+// also hold the staged cell block) fit three workgroups per CU.  The channel
+// kernel keeps the 4 x 8 x 8 x-tile with direct stencil loads (its wall ghosts
+// need all five components of a mirror cell at once); in FP64 that tile's face
+// field already fills 46 KB, so its phase 2 goes per face (gp_data) rather than
+// drop to two workgroups per CU.
+template <typename T, int DIR, bool CHAN>
+struct FusedTile {
+  using TG = TileGeom<DIR>;
+  static constexpr bool kStaged = false;
+};
+template <typename T>
+struct FusedTile<T, 0, false> {
+  using TG = TileGeomB<0, 2, 16, 8>;
+  static constexpr bool kStaged = true;
+};
+template <typename T, int DIR, bool CHAN>
+constexpr bool kSharedRows = !(DIR == 0 && CHAN && sizeof(T) == sizeof(double));
+template <typename T, int DIR, bool CHAN>
+constexpr int kRowBuf =
+    kSharedRows<T, DIR, CHAN> ? 2 * RowGeom<DIR, typename FusedTile<T, DIR, CHAN>::TG>::NBUF : 1;
 
 // Per-face phase 2: each face sums its own 5 x 5 neighbourhood (gp_data), one t1
 // Gauss point at a time; with a stretched y (channel), y is t1 of x-faces.
-template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, class TG>
 __device__ __forceinline__ void per_face_phase2(const Geo& g, const T* ff, const int* tp, int gy, bool ys, T* Fs,
                                                 T* dFs) {
   static_assert(DIR == 0, "per-face phase 2 serves x-faces, whose t1 is the stretched y");
-  using TG = TileGeom<DIR>;
   constexpr int A1 = (DIR + 1) % 3, A2 = (DIR + 2) % 3;
   const int centre = (tp[0] + TG::HX) + (tp[1] + TG::HY) * TG::FX + (tp[2] + TG::HZ) * TG::FX * TG::FY;
   const int corner = centre - 2 * TG::S[A1] - 2 * TG::S[A2];
@@ -53,7 +62,7 @@ __device__ __forceinline__ void per_face_phase2(const Geo& g, const T* ff, const
       w1 = T(ym_gp_w(g, gy, m));
     }
     T Qg[2][5], Dg[2][3][5];
-    gp_data<T, DIR>(ff, corner, m, i1, i2, i2, Qg, Dg);
+    gp_data<T, DIR, TG>(ff, corner, m, i1, i2, i2, Qg, Dg);
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
       T F[5], dF[5];
@@ -70,18 +79,24 @@ __device__ __forceinline__ void per_face_phase2(const Geo& g, const T* ff, const
 template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool CHAN, bool OFF32>
 __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                                 T* ff, T* rowbuf, int ntx, int nty, int ntz, int nper) {
-  using TG = TileGeom<DIR>;
-  using RG = RowGeom<DIR>;
+  using FT = FusedTile<T, DIR, CHAN>;
+  using TG = typename FT::TG;
+  using RG = RowGeom<DIR, TG>;
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
-  tile_origin<DIR>(tile, ntx, nty, ntz, x0, y0, z0);
+  tile_origin<DIR, TG>(tile, ntx, nty, ntz, x0, y0, z0);
   // channel: y-face rows run from the bottom wall face (row -1) to the top one
   if (CHAN && DIR == 1) y0 -= 1;
   double dn_scale = g.inv_h[DIR];
   if (CHAN && DIR == 1 && g.stretch_y) dn_scale = ym_face_inv(g, y0 + 1);
 
-  face_field_tile<T, DIR, CHAN, TileGeom<DIR>, OFF32>(g, q, ff, x0, y0, z0, dn_scale);
+  if constexpr (FT::kStaged) {
+    static_assert(RowGeom<DIR, TG>::NBUF * 2 >= (TG::BX + 5) * TG::FY * TG::FZ, "cell block fits the row buffers");
+    face_field_tile_x_staged<T, TG, OFF32>(g, q, ff, rowbuf, x0, y0, z0, dn_scale);
+  } else {
+    face_field_tile<T, DIR, CHAN, TG, OFF32>(g, q, ff, x0, y0, z0, dn_scale);
+  }
   __syncthreads();
 
   const int tid = threadIdx.x;
@@ -96,9 +111,9 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   const bool ys = CHAN && DIR != 1 && g.stretch_y;
   const T iR = T(g.inv_h[RG::AR]);
   T Fs[5] = {0, 0, 0, 0, 0}, dFs[5] = {0, 0, 0, 0, 0};
-  if constexpr (!kSharedRows<T, DIR>) {
+  if constexpr (!kSharedRows<T, DIR, CHAN>) {
     if (!active) return;
-    per_face_phase2<T, DIR, STAGE2, VAR_MU>(g, ff, tp, gy, ys, Fs, dFs);
+    per_face_phase2<T, DIR, STAGE2, VAR_MU, TG>(g, ff, tp, gy, ys, Fs, dFs);
   } else {
 #pragma unroll 1
   for (int pt = 0; pt < 2; ++pt) {  // S Gauss point (-, +)
@@ -113,10 +128,10 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
       // two row buffers in turn: the rows of the next component are written while
       // no thread can still be reading the buffer from two components back
       T* buf = rowbuf + ((pt + k) & 1) * RG::NBUF;
-      rows_pass<T, DIR>(ff, buf, pt, k);
+      rows_pass<T, DIR, TG>(ff, buf, pt, k);
       __syncthreads();
       T vR[2], dR[2], dS[2], dn[2];
-      rows_combine<T, DIR>(buf, tp[DIR], tp[RG::AS], tp[RG::AR], vR, dR, dS, dn);
+      rows_combine<T, DIR, TG>(buf, tp[DIR], tp[RG::AS], tp[RG::AR], vR, dR, dS, dn);
       // finish this component's combination before the next pass starts: left to
       // itself the scheduler keeps the rows of all five components in registers
       // and combines them at the end, which spills (10% slower)
@@ -178,8 +193,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_FLUX_WAVES : HGKS_FLUX_
 flux_fused_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop, int ntx,
                   int nty, int ntz, int nper) {
   if (*stop) return;
-  __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  __shared__ __align__(16) T ff[10 * FusedTile<T, DIR, false>::TG::NFF];
+  __shared__ T rowbuf[kRowBuf<T, DIR, false>];
   flux_fused_body<T, DIR, STAGE2, false, false, OFF32>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
@@ -188,8 +203,8 @@ __global__ void __launch_bounds__(256) flux_fused_varmu_kernel(Geo g, const doub
                                                                T* __restrict__ fl, const int* __restrict__ stop,
                                                                int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
-  __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  __shared__ __align__(16) T ff[10 * FusedTile<T, DIR, false>::TG::NFF];
+  __shared__ T rowbuf[kRowBuf<T, DIR, false>];
   flux_fused_body<T, DIR, false, true, false, OFF32>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
@@ -202,23 +217,20 @@ flux_fused_chan_kernel(Geo g, const double* __restrict__ q,
                                                               T* __restrict__ fl, const int* __restrict__ stop,
                                                               int ntx, int nty, int ntz, int nper) {
   if (*stop) return;
-  __shared__ T ff[10 * TileGeom<DIR>::NFF];
-  __shared__ T rowbuf[kRowBuf<T, DIR>];
+  __shared__ T ff[10 * FusedTile<T, DIR, true>::TG::NFF];
+  __shared__ T rowbuf[kRowBuf<T, DIR, true>];
   flux_fused_body<T, DIR, STAGE2, VAR_MU, true, false>(g, q, fl, ff, rowbuf, ntx, nty, ntz, nper);
 }
 
-template <int DIR>
-void tile_grid(const Geo& g, int& ntx, int& nty, int& ntz, int& nper) {
-  using TG = TileGeom<DIR>;
+template <typename T, int DIR, bool CHAN>
+static void tile_grid(const Geo& g, int& ntx, int& nty, int& ntz, int& nper) {
+  using TG = typename FusedTile<T, DIR, CHAN>::TG;
   ntx = (g.n[0] + TG::BX - 1) / TG::BX;
   // with walls in y there are ny + 1 rows of y-faces (one tile row each)
   nty = (g.n[1] + (DIR == 1 && g.wall_y ? 1 : 0) + TG::BY - 1) / TG::BY;
   ntz = (g.n[2] + TG::BZ - 1) / TG::BZ;
   nper = (ntx * nty * ntz + 7) / 8;
 }
-template void tile_grid<0>(const Geo&, int&, int&, int&, int&);
-template void tile_grid<1>(const Geo&, int&, int&, int&, int&);
-template void tile_grid<2>(const Geo&, int&, int&, int&, int&);
 
 // Boxes of up to 2^29 cells address every field with 32-bit byte offsets.
 constexpr long long kOff32MaxCells = 1LL << 29;
@@ -226,8 +238,12 @@ constexpr long long kOff32MaxCells = 1LL << 29;
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
 static void launch_dir(const Geo& g, const double* q, T* fl, const int* stop, hipStream_t st) {
   int ntx, nty, ntz, nper;
-  tile_grid<DIR>(g, ntx, nty, ntz, nper);
-  if (g.wall_y || g.stretch_y)
+  const bool chan = g.wall_y || g.stretch_y;
+  if (chan)
+    tile_grid<T, DIR, true>(g, ntx, nty, ntz, nper);
+  else
+    tile_grid<T, DIR, false>(g, ntx, nty, ntz, nper);
+  if (chan)
     flux_fused_chan_kernel<T, DIR, STAGE2, VAR_MU><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, ntx,
                                                                                                   nty, ntz, nper);
   else if (g.N <= kOff32MaxCells) {

@@ -3,13 +3,17 @@
 // recomputes exactly the forward arithmetic.
 //
 // A workgroup of 256 threads owns a tile of 256 faces of direction DIR plus a
-// halo of two faces along both tangential axes.  x-faces use a 4 x 8 x 8 tile
-// (halo in y and z), y- and z-faces 32 x 8 along x and the other tangential axis,
-// so that x, the contiguous axis, is at least four faces wide in every load (an
-// x-face tile one face wide reads each six-cell x-stencil from its own cache
-// lines and runs 40% slower).  Square 16 x 16 tangential tiles, which evaluate
-// fewer halo faces (1.56 instead of 1.69 per face), measured no faster.
+// halo of two faces along both tangential axes.  y- and z-faces use 32 x 8 tiles
+// along x and the other tangential axis, so that x, the contiguous axis, is wide
+// in every load; square 16 x 16 tangential tiles, which evaluate fewer halo faces
+// (1.56 instead of 1.69 per face), measured no faster.  x-face tiles are
+// necessarily short in x.  TileGeom's 4 x 8 x 8 x-tile loads each entry's
+// six-cell x-stencil directly (a one-face-wide tile doing so runs 40% slower);
+// the periodic flux kernel instead uses a 2 x 16 x 8 x-tile whose cell block is
+// staged through LDS (face_field_tile_x_staged).
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.hpp"
 
@@ -187,6 +191,101 @@ __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __re
     for (int k = 0; k < 5; ++k) {
       ff[k * TG::NFF + e] = Q0[k];
       ff[(5 + k) * TG::NFF + e] = Dn[k];
+    }
+  }
+}
+
+// Phase 1 for x-faces staged through LDS.  An x-face tile is only a few faces
+// long in x, the contiguous axis, so per-entry stencil loads touch many cache
+// lines per instruction.  Here the workgroup loads the tile's cell block (x from
+// x0-2 to x0+BX+2, the tangential extent with its halo) one component at a time
+// into blk, x fastest, so each load instruction covers consecutive runs of cells;
+// every entry then takes its six-cell stencil from LDS and keeps Q_l, Q_r and D_n
+// in registers until all five components are in, when the compatibility state is
+// formed.  blk holds BX+5 by FY by FZ values (deviations from the reference
+// state, rounded to T as in normal_stencil).  The caller synchronizes after.
+template <typename T, class TG, bool OFF32>
+__device__ __forceinline__ void face_field_tile_x_staged(const Geo& g, const double* __restrict__ q, T* ff, T* blk,
+                                                         int x0, int y0, int z0, double dn_scale) {
+  static_assert(TG::HX == 0 && TG::HY == 2 && TG::HZ == 2, "x-face tile");
+  constexpr int CX = TG::BX + 5;                 // cells along x
+  constexpr int NB = CX * TG::FY * TG::FZ;       // cells of the block
+  constexpr int NL = (NB + 255) / 256;           // block cells per thread
+  const T ih12 = T(dn_scale * (1.0 / 12.0));
+  const int tid = threadIdx.x;
+  // element offsets of this thread's block cells (the last slot may be empty);
+  // a block that crosses no periodic boundary (most tiles) needs no wrapping
+  long long off[NL];
+  const bool inner = x0 >= 2 && x0 + CX - 2 <= g.n[0] && y0 >= 2 && y0 + TG::FY - 2 <= g.n[1] && z0 >= 2 &&
+                     z0 + TG::FZ - 2 <= g.n[2];
+  if (inner) {
+    const long long c0 = (long long)(x0 - 2) + (long long)(y0 - 2) * g.stride[1] + (long long)(z0 - 2) * g.stride[2];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int b = tid + 256 * i < NB ? tid + 256 * i : NB - 1;
+      const int bx = b % CX, r = b / CX, by = r % TG::FY, bz = r / TG::FY;
+      off[i] = c0 + (long long)bx + (long long)by * g.stride[1] + (long long)bz * g.stride[2];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int b = tid + 256 * i < NB ? tid + 256 * i : NB - 1;
+      const int bx = b % CX, r = b / CX, by = r % TG::FY, bz = r / TG::FY;
+      const int cx = wrap_coord(x0 - 2 + bx, g.n[0]);
+      const int cy = wrap_coord(y0 - 2 + by, g.n[1]);
+      const int cz = wrap_coord(z0 - 2 + bz, g.n[2]);
+      off[i] = (long long)cx + (long long)cy * g.stride[1] + (long long)cz * g.stride[2];
+    }
+  }
+  auto load = [&](int k, double* val) {
+    const double* f = q + (long long)k * g.N;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      val[i] = OFF32 ? *(const double*)((const char*)f + unsigned(off[i]) * 8u) : f[off[i]];
+  };
+  // one thread per block row (fixed y, z): it reads the row's CX cells once and
+  // reconstructs the BX entries of that row (a row stride of CX doubles keeps the
+  // reads of sixteen consecutive lanes on distinct LDS banks)
+  constexpr int NR = TG::FY * TG::FZ;
+  static_assert(NR <= 256 && TG::FX == TG::BX, "one block row per thread");
+  T Ql[TG::BX][5], Qr[TG::BX][5], Dn[TG::BX][5];
+  double val[NL];
+  load(0, val);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      if (tid + 256 * i < NB) blk[tid + 256 * i] = T(val[i] - ref);
+    __syncthreads();
+    // the next component's loads are in flight while this one is reconstructed
+    if (k < 4) load(k + 1, val);
+    if (tid < NR) {
+      const T* c = blk + CX * tid;
+      T v[CX];
+#pragma unroll
+      for (int m = 0; m < CX; ++m) v[m] = c[m];
+#pragma unroll
+      for (int ex = 0; ex < TG::BX; ++ex) normal_recon(v + ex, ih12, Ql[ex][k], Qr[ex][k], Dn[ex][k]);
+    }
+    __syncthreads();
+  }
+  if (tid < NR) {
+    T Q0[TG::BX][5];
+#pragma unroll
+    for (int ex = 0; ex < TG::BX; ++ex) compat_dev(g, Ql[ex], Qr[ex], Q0[ex]);
+    // the row's BX entries are adjacent in ff: one vector store per field
+    static_assert(TG::BX == 2 && TG::NFF % 2 == 0, "pairs of entries");
+    using T2 = typename std::conditional<sizeof(T) == sizeof(double), double2, float2>::type;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      T2 a, d;
+      a.x = Q0[0][k];
+      a.y = Q0[1][k];
+      d.x = Dn[0][k];
+      d.y = Dn[1][k];
+      *(T2*)(ff + k * TG::NFF + 2 * tid) = a;
+      *(T2*)(ff + (5 + k) * TG::NFF + 2 * tid) = d;
     }
   }
 }
