@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
     const int pn = pc[DIR];
     // global cell: the normal axis starts two cells before the tile's first face
     // row, the tangential axes at the patch origin (halo of two)
-    const int gc[3] = {wrapmod(x0 - 2 + px, g.n[0]), wrapmod(y0 - 2 + py, g.n[1]), wrapmod(z0 - 2 + pz, g.n[2])};
+    const int gc[3] = {wrap_coord(x0 - 2 + px, g.n[0]), wrap_coord(y0 - 2 + py, g.n[1]), wrap_coord(z0 - 2 + pz, g.n[2])};
     const long long cell = (long long)gc[0] + (long long)gc[1] * g.stride[1] + (long long)gc[2] * g.stride[2];
     double acc[5] = {0, 0, 0, 0, 0};
     const int ilo = pn - 5 > 0 ? pn - 5 : 0, ihi = pn < BN - 1 ? pn : BN - 1;

@@ -195,8 +195,8 @@ __global__ void __launch_bounds__(256) flux_z_vjp_kernel(Geo g, const double* __
     const int i1 = e % TG::P, i2 = e / TG::P;
     int c[3];
     c[DIR] = on;
-    c[TG::A1] = wrapmod(o1 + i1 - 2, g.n[TG::A1]);
-    c[TG::A2] = wrapmod(o2 + i2 - 2, g.n[TG::A2]);
+    c[TG::A1] = wrap_coord(o1 + i1 - 2, g.n[TG::A1]);
+    c[TG::A2] = wrap_coord(o2 + i2 - 2, g.n[TG::A2]);
     const long long sn = g.stride[DIR];
     const long long base =
         (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2] - (long long)on * sn;
