@@ -29,6 +29,30 @@ template <> struct AdjTile<0> { static constexpr int B[3] = {2, 16, 8}; };
 template <int DIR>
 using AdjGeom = TileGeomB<DIR, AdjTile<DIR>::B[0], AdjTile<DIR>::B[1], AdjTile<DIR>::B[2]>;
 
+// Tile order of the adjoint.  y- and z-face tiles are numbered with the normal
+// axis slowest, so that the tiles whose footprints share cells along the normal
+// run far apart in time and their atomic adds into lambda do not contend (z-faces
+// 11% faster, y-faces 4%).  x-face tiles keep the forward order, normal axis
+// fastest: there the L2 reuse of the shared x-stencil matters more (the other
+// order made them 20-45% slower).
+template <int DIR, class TG>
+__device__ __forceinline__ void adj_tile_origin(int tile, int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
+  if (DIR == 0) {
+    tile_origin<DIR, TG>(tile, ntx, nty, ntz, x0, y0, z0);
+    return;
+  }
+  const int nt1 = ntx, nt2 = DIR == 1 ? ntz : nty;  // tangential tile counts (x first)
+  const int a = tile % nt1, r = tile / nt1, b = r % nt2, n = r / nt2;
+  x0 = a * TG::BX;
+  if (DIR == 1) {
+    y0 = n * TG::BY;
+    z0 = b * TG::BZ;
+  } else {
+    y0 = b * TG::BY;
+    z0 = n * TG::BZ;
+  }
+}
+
 // T is the arithmetic of the recomputed forward and of its reverse (double, or
 // float for the FP32-flux form); the cotangents A, B and lambda stay in double.
 template <typename T, int DIR, bool NEED_F>
@@ -44,7 +68,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) f
   const int tile = tile_of_block(nper);
   if (tile >= ntx * nty * ntz) return;
   int x0, y0, z0;
-  tile_origin<DIR, TG>(tile, ntx, nty, ntz, x0, y0, z0);
+  adj_tile_origin<DIR, TG>(tile, ntx, nty, ntz, x0, y0, z0);
   const int tid = threadIdx.x;
 
   face_field_tile<T, DIR, false, TG>(g, q, ff, x0, y0, z0, g.inv_h[DIR]);
