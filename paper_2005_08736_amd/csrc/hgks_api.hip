@@ -228,7 +228,12 @@ void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop)
   }
 }
 
-// adjoint of the face fluxes of all three directions (one timed launch each)
+// scratch of the smooth-mode operator VJP: 10 N doubles of face-field cotangents
+// in the face-flux arrays, which the step adjoint no longer needs once Q* is formed
+// (30 N values of the flux type: 240 B per cell in FP64, 120 in the FP32 form)
+double* vjp_scratch(hgks_handle* h) { return reinterpret_cast<double*>(h->fl); }
+
+// adjoint of the face fluxes of all three directions (one timed launch pair each)
 void operator_vjp(hgks_handle* h, const double* q, const double* A, const double* B, double cLA, double cLB,
                   double cDA, double cDB, double* lam) {
   for (int d = 0; d < 3; ++d) {
@@ -236,7 +241,7 @@ void operator_vjp(hgks_handle* h, const double* q, const double* A, const double
     if (h->p.mode == HGKS_MODE_WENOZ)
       launch_operator_vjp_z(h->geo, d, q, A, B, cLA, cLB, cDA, cDB, &h->ctrl->dt, lam, h->stream);
     else
-      launch_operator_vjp(h->geo, d, f32(h), q, A, B, cLA, cLB, cDA, cDB, lam, h->stream);
+      launch_operator_vjp(h->geo, d, f32(h), q, A, B, cLA, cLB, cDA, cDB, vjp_scratch(h), lam, h->stream);
     prof_end(h, on);
   }
 }
@@ -438,7 +443,9 @@ int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* la
   launch_set_dt(h->ctrl, dt, st);
   all_fluxes(h, q_n, false, &h->ctrl->zero);
   stage1(h, q_n, h->qs, -1);
-  // lambda* = (ddL/dQ)^T(Q*) (dt^2/3 lambda)
+  // lambda* = (ddL/dQ)^T(Q*) (dt^2/3 lambda); the operator VJP's scratch starts
+  // from zeros (it leaves it cleared)
+  if (h->p.mode == HGKS_MODE_SMOOTH) launch_fill(vjp_scratch(h), 0.0, 10 * g.N, st);
   launch_fill(h->lam_star, 0.0, n5, st);
   operator_vjp(h, h->qs, lam_np1, nullptr, 0.0, 0.0, dt * dt / 3.0, 0.0, h->lam_star);
   // lambda_n = lambda + lambda* + (dL/dQ)^T(Q^n) (dt lambda + dt/2 lambda*)

@@ -28,7 +28,7 @@ void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, double* 
 void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop, const double* dtp,
                    hipStream_t st);
 void launch_operator_vjp(const Geo& g, int dir, bool f32, const double* q, const double* A, const double* B,
-                         double cLA, double cLB, double cDA, double cDB, double* lam, hipStream_t st);
+                         double cLA, double cLB, double cDA, double cDB, double* G, double* lam, hipStream_t st);
 void launch_operator_vjp_z(const Geo& g, int dir, const double* q, const double* A, const double* B, double cLA,
                            double cLB, double cDA, double cDB, const double* dtp, double* lam, hipStream_t st);
 void launch_axpby(double a, const double* X, double b, const double* Y, double* out, long long n, hipStream_t st);
