@@ -58,6 +58,12 @@ CASES = {
                                                       lz=1.3 * math.pi, mu_ref=3e-3, prandtl=0.7), q))(
         smooth_field(12, 10, 8, seed=21)),
     "tgv32": lambda: (cases.tgv_params(32), cases.tgv_state(32)),
+    # y and z axes of at least 21 cells that are not multiples of the y/z adjoint's
+    # 16-face runs: the last run along each is partial (8 and 6 faces), and its
+    # directly written cells border cells that take atomic adds
+    "ragged14x24x22": lambda: (lambda q: (cases.params(nx=14, ny=24, nz=22, lx=1.1 * math.pi, ly=2 * math.pi,
+                                                        lz=1.8 * math.pi, mu_ref=3e-3, prandtl=0.7), q))(
+        smooth_field(14, 24, 22, seed=22)),
 }
 
 
