@@ -139,7 +139,9 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
  * the derivative sign(x) with sign(0) = +1.  HGKS_E_UNSUPPORTED otherwise (mode
  * Z with the FP32-flux form, mu(T) in smooth mode, walls, stretching, body
  * force).  Enqueued on the handle's stream, no synchronization; the bound state
- * is not touched. */
+ * is not touched.  Uses the workspace: the smooth mode keeps its face-field
+ * cotangents (10 N doubles) in the face-flux arrays, so after the call those
+ * arrays hold zeros, not the step's face fluxes. */
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
 
 /* Global FP64 diagnostics of the bound state (Sec. 3.1, 3.4): out (host) receives
