@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hgks {
 
 // Grid and gas constants, passed to every kernel by value.
@@ -129,18 +131,21 @@ __host__ __device__ __forceinline__ void zdep(T& x, const U& after) {
 }
 
 // 1/a without the scaling steps of IEEE division, for a whose reciprocal is a
-// normal number (densities, sound speeds).  FP64: the hardware estimate refined
-// by two Newton steps r <- r + r (1 - a r), within about an ulp of the rounded
-// quotient; FP32: the hardware estimate (1 ulp).
+// normal number (densities, sound speeds, sums of positive weights).  FP64: the
+// hardware estimate refined by two Newton steps r <- r + r (1 - a r), within
+// about an ulp of the rounded quotient; FP32: the hardware estimate (1 ulp).
+// Other arithmetic types (the forward tangents of the mode-Z adjoint) divide.
 template <typename T>
 __host__ __device__ __forceinline__ T recip(T a) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  if constexpr (sizeof(T) == sizeof(double)) {
+  if constexpr (std::is_same<T, double>::value) {
     double r = __builtin_amdgcn_rcp(a);
     r = fma(r, fma(-a, r, 1.0), r);
     return fma(r, fma(-a, r, 1.0), r);
-  } else {
+  } else if constexpr (std::is_same<T, float>::value) {
     return __builtin_amdgcn_rcpf(a);
+  } else {
+    return T(1) / a;
   }
 #else
   return T(1) / a;

@@ -26,7 +26,8 @@ namespace hgks {
 // ---------------------------------------------------------------------------
 template <typename T>
 __host__ __device__ __forceinline__ T zratio(T tau5, T b, T eps, int p) {
-  T r = tau5 / (b + eps);
+  T r = tau5 * recip(b + eps);
+  if (p == 2) return r * r;  // the usual exponent, without a loop
   T out = r;
   for (int i = 1; i < p; ++i) out = out * r;
   return out;
@@ -45,8 +46,14 @@ __host__ __device__ __forceinline__ void zratios(T tau5, T b0, T b1, T b2, T eps
   } else {
     const T d0 = b0 + eps, d1 = b1 + eps, d2 = b2 + eps;
     const T d01 = d0 * d1;
-    const T t = tau5 / (d01 * d2);
+    const T t = tau5 * recip(d01 * d2);
     const T x0 = t * (d1 * d2), x1 = t * (d0 * d2), x2 = t * d01;
+    if (p == 2) {  // the usual exponent, without a loop
+      r0 = x0 * x0;
+      r1 = x1 * x1;
+      r2 = x2 * x2;
+      return;
+    }
     r0 = x0;
     r1 = x1;
     r2 = x2;
@@ -80,7 +87,7 @@ __host__ __device__ __forceinline__ void weno_z_right(const T* v, T eps, int p, 
   T a0 = T(0.1) * (T(1) + r0);
   T a1 = T(0.6) * (T(1) + r1);
   T a2 = T(0.3) * (T(1) + r2);
-  const T isum = T(1) / (a0 + a1 + a2);
+  const T isum = recip(a0 + a1 + a2);
   T w0 = a0 * isum, w1 = a1 * isum, w2 = a2 * isum;
   T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
   T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
@@ -101,7 +108,7 @@ __host__ __device__ __forceinline__ void weno_z_edges(const T* v, T eps, int p, 
   zratios(tau5, b0, b1, b2, eps, p, r0, r1, r2);
   {
     T a0 = T(0.1) * (T(1) + r0), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r2);
-    const T isum = T(1) / (a0 + a1 + a2);
+    const T isum = recip(a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
@@ -110,7 +117,7 @@ __host__ __device__ __forceinline__ void weno_z_edges(const T* v, T eps, int p, 
   {
     // reversed line (v4, v3, v2, v1, v0): indicators (b2, b1, b0)
     T a0 = T(0.1) * (T(1) + r2), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r0);
-    const T isum = T(1) / (a0 + a1 + a2);
+    const T isum = recip(a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[4] - T(7.0 / 6.0) * v[3] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[3] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[1];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[1] - T(1.0 / 6.0) * v[0];
