@@ -6,7 +6,10 @@ exercised.  The first box is below 2^29 cells, where the flux kernels read the
 state through 32-bit byte offsets (up to 3.5 GB into a field); the second is
 above it and takes their 64-bit addressing.  The oracle checks dt over the whole
 box and Q^{n+1} at sampled cells (near the high corners too) from windows
-holding each cell's two-stage dependence."""
+holding each cell's two-stage dependence.  The step adjoint runs on the first box
+too, with its own scratch array of face cotangents (10 N doubles) past 2^31
+values; sampled entries of its output are checked against the oracle's JVP on
+windows of 25^3 cells."""
 import math
 import sys
 
@@ -25,18 +28,11 @@ def announce(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("nz", [416, 528])
-def test_large_box_64bit_offsets_sampled_step(nz):
-    if not torch.cuda.is_available():
-        raise RuntimeError("GPU test started without a ROCm device")
-    dev = torch.device("cuda:0")
-    nx, ny = 1024, 1024
+def large_field(nx, ny, nz, dev):
+    """Parameters and a smooth periodic state (Taylor-Green-like velocity, varying
+    density and pressure), built on the device from broadcast 1-D factors."""
     h = 2 * math.pi / nx
     p = cases.params(nx=nx, ny=ny, nz=nz, lx=nx * h, ly=ny * h, lz=nz * h, mu_ref=1.0 / 1600, prandtl=0.72)
-    announce(f"large box {nx}x{ny}x{nz} ({nx * ny * nz:.3e} cells), workspace "
-             f"{hgks.workspace_bytes(p) / 1e9:.1f} GB")
-    # a smooth periodic field (Taylor-Green-like velocity, varying density and
-    # pressure), built on the device from broadcast 1-D factors
     x = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * h
     y = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * h
     z = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * h * (nx / nz)
@@ -53,6 +49,18 @@ def test_large_box_64bit_offsets_sampled_step(nz):
     q[4] = pr / (gamma - 1) + 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2)
     q[1:4] *= q[0]
     del pr
+    return p, h, q
+
+
+@pytest.mark.parametrize("nz", [416, 528])
+def test_large_box_64bit_offsets_sampled_step(nz):
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    dev = torch.device("cuda:0")
+    nx, ny = 1024, 1024
+    p, h, q = large_field(nx, ny, nz, dev)
+    announce(f"large box {nx}x{ny}x{nz} ({nx * ny * nz:.3e} cells), workspace "
+             f"{hgks.workspace_bytes(p) / 1e9:.1f} GB")
     q0 = q.cpu().numpy()
     s = hgks.Solver(p, q)
     dts = s.step(1, return_dt=True)
@@ -77,4 +85,56 @@ def test_large_box_64bit_offsets_sampled_step(nz):
         assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(np.abs(ref), 1.0)), (c, got - ref)
     s.close()
     del s, q
+    torch.cuda.empty_cache()
+
+
+def test_large_box_step_vjp_sampled():
+    """lam_n = (dQ^{n+1}/dQ^n)^T lam at sampled cells and components of the
+    1024 x 1024 x 416 box, against <lam, J e_i> from the oracle's JVP of one step
+    on the 25^3 window around the cell (J e_i reaches six cells, and its entries
+    there depend on the state six cells further)."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    dev = torch.device("cuda:0")
+    nx, ny, nz = 1024, 1024, 416
+    p, h, q = large_field(nx, ny, nz, dev)
+    announce(f"large box step adjoint {nx}x{ny}x{nz} ({nx * ny * nz:.3e} cells)")
+    # a smooth cotangent field, different in each component
+    x = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * h
+    y = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * h
+    z = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * h * (nx / nz)
+    lam = torch.empty_like(q)
+    for k in range(5):
+        lam[k] = (torch.sin(x + 0.7 * k)[None, None, :] * torch.cos(2 * y + 0.3 * k)[None, :, None]
+                  + 0.5 * torch.cos(z - 0.2 * k)[:, None, None])
+    dt = 2e-4
+    s = hgks.Solver(p, q)
+    lam_n = s.step_vjp(q, dt, lam)
+    torch.cuda.synchronize()
+    pw = dict(p)
+    pw.update(nx=25, ny=25, nz=25, lx=25 * h, ly=25 * h, lz=25 * h)
+    rng = np.random.default_rng(5416)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))) for _ in range(3)]
+    pts += [(nx - 1, ny - 1, nz - 1), (0, ny - 2, nz - 1), (6, 3, 0)]
+    for n_, c in enumerate(pts):
+        comp = n_ % 5
+        ii = torch.tensor(np.arange(c[0] - 12, c[0] + 13) % nx, device=dev)
+        jj = torch.tensor(np.arange(c[1] - 12, c[1] + 13) % ny, device=dev)
+        kk = torch.tensor(np.arange(c[2] - 12, c[2] + 13) % nz, device=dev)
+
+        def window(a):
+            return a.index_select(1, kk).index_select(2, jj).index_select(3, ii).cpu().numpy()
+
+        qw, lw = window(q), window(lam)
+        v = np.zeros_like(qw)
+        v[comp, 12, 12, 12] = 1.0
+        _, jv = oracle.jvp(pw, qw, v, [dt])
+        ref = float(np.sum(lw * jv))
+        scale = float(np.sum(np.abs(lw * jv)))
+        got = float(lam_n[comp, c[2], c[1], c[0]].item())
+        announce(f"  cell {c} component {comp}: adjoint {got:.15e}  oracle JVP {ref:.15e}  "
+                 f"rel to scale {abs(got - ref) / scale:.2e}")
+        assert abs(got - ref) <= 1e-12 * scale, (c, comp, got, ref, scale)
+    s.close()
+    del s, q, lam, lam_n
     torch.cuda.empty_cache()
