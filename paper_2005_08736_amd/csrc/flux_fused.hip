@@ -92,8 +92,12 @@ __device__ __forceinline__ void flux_fused_body(const Geo& g, const double* __re
   if (CHAN && DIR == 1 && g.stretch_y) dn_scale = ym_face_inv(g, y0 + 1);
 
   if constexpr (FT::kStaged) {
-    static_assert(RowGeom<DIR, TG>::NBUF * 2 >= (TG::BX + 5) * TG::FY * TG::FZ, "cell block fits the row buffers");
-    face_field_tile_x_staged<T, TG, OFF32>(g, q, ff, rowbuf, x0, y0, z0, dn_scale);
+    // FP64 stages two components per round, in the face field's space (5% faster
+    // than one per round); FP32 one per round in the row buffers (2% faster)
+    constexpr int NB = (TG::BX + 5) * TG::FY * TG::FZ;
+    constexpr bool pairs = sizeof(T) == sizeof(double);
+    static_assert(pairs ? 10 * TG::NFF >= 2 * NB : 2 * RowGeom<DIR, TG>::NBUF >= NB, "cell blocks fit");
+    face_field_tile_x_staged<T, TG, OFF32, pairs>(g, q, ff, pairs ? ff : rowbuf, x0, y0, z0, dn_scale);
   } else {
     face_field_tile<T, DIR, CHAN, TG, OFF32>(g, q, ff, x0, y0, z0, dn_scale);
   }

@@ -203,8 +203,10 @@ __device__ __forceinline__ void face_field_tile(const Geo& g, const double* __re
 // every entry then takes its six-cell stencil from LDS and keeps Q_l, Q_r and D_n
 // in registers until all five components are in, when the compatibility state is
 // formed.  blk holds BX+5 by FY by FZ values (deviations from the reference
-// state, rounded to T as in normal_stencil).  The caller synchronizes after.
-template <typename T, class TG, bool OFF32>
+// state, rounded to T as in normal_stencil), or twice that with PAIRS, which
+// stages two components per round (three rounds instead of five).  The caller
+// synchronizes after.
+template <typename T, class TG, bool OFF32, bool PAIRS>
 __device__ __forceinline__ void face_field_tile_x_staged(const Geo& g, const double* __restrict__ q, T* ff, T* blk,
                                                          int x0, int y0, int z0, double dn_scale) {
   static_assert(TG::HX == 0 && TG::HY == 2 && TG::HZ == 2, "x-face tile");
@@ -249,6 +251,43 @@ __device__ __forceinline__ void face_field_tile_x_staged(const Geo& g, const dou
   constexpr int NR = TG::FY * TG::FZ;
   static_assert(NR <= 256 && TG::FX == TG::BX, "one block row per thread");
   T Ql[TG::BX][5], Qr[TG::BX][5], Dn[TG::BX][5];
+  if constexpr (PAIRS) {
+  // two components per round (blk holds two blocks): three rounds, six barriers
+  double val2[2][NL];
+  load(0, val2[0]);
+  load(1, val2[1]);
+#pragma unroll
+  for (int k0 = 0; k0 < 5; k0 += 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = k0 + j;
+      if (k < 5) {
+        const double ref = k == 0 ? g.rho_ref : (k == 4 ? g.E_ref : 0.0);
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+          if (tid + 256 * i < NB) blk[j * NB + tid + 256 * i] = T(val2[j][i] - ref);
+      }
+    }
+    __syncthreads();
+    if (k0 + 2 < 5) load(k0 + 2, val2[0]);
+    if (k0 + 3 < 5) load(k0 + 3, val2[1]);
+    if (tid < NR) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + j;
+        if (k < 5) {
+          const T* c = blk + j * NB + CX * tid;
+          T v[CX];
+#pragma unroll
+          for (int m = 0; m < CX; ++m) v[m] = c[m];
+#pragma unroll
+          for (int ex = 0; ex < TG::BX; ++ex) normal_recon(v + ex, ih12, Ql[ex][k], Qr[ex][k], Dn[ex][k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  } else {
   double val[NL];
   load(0, val);
 #pragma unroll
@@ -269,6 +308,7 @@ __device__ __forceinline__ void face_field_tile_x_staged(const Geo& g, const dou
       for (int ex = 0; ex < TG::BX; ++ex) normal_recon(v + ex, ih12, Ql[ex][k], Qr[ex][k], Dn[ex][k]);
     }
     __syncthreads();
+  }
   }
   if (tid < NR) {
     T Q0[TG::BX][5];
