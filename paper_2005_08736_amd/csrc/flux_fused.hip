@@ -20,10 +20,10 @@
 namespace hgks {
 
 // Tile shapes.  y- and z-faces use TileGeom (32 x 8 along x and the other
-// tangential axis).  x-faces of the periodic kernels use a 2 x 16 x 8 tile whose
-// phase 1 is staged through LDS (face_field_tile_x_staged) and whose phase 2
-// shares rows: its face field (38 KB in FP64) and two row buffers (15 KB, which
-// also hold the staged cell block) fit three workgroups per CU.  The channel
+// tangential axis).  FP64 x-faces of the periodic kernels use a 2 x 16 x 8 tile whose
+// phase 1 is staged through LDS (face_field_tile_x_staged, the cell blocks in
+// the face field's own space) and whose phase 2 shares rows: its face field
+// (38 KB) and two row buffers (15 KB) fit three workgroups per CU.  The channel
 // kernel keeps the 4 x 8 x 8 x-tile with direct stencil loads (its wall ghosts
 // need all five components of a mirror cell at once); in FP64 that tile's face
 // field already fills 46 KB, so its phase 2 goes per face (gp_data) rather than
@@ -36,6 +36,14 @@ struct FusedTile {
 template <typename T>
 struct FusedTile<T, 0, false> {
   using TG = TileGeomB<0, 2, 16, 8>;
+  static constexpr bool kStaged = true;
+};
+// FP32 x-faces: a 4 x 8 x 8 tile (2.25 face-field entries per face instead of
+// 1.88) writes 16-byte runs of each output field instead of 8-byte ones, and
+// its staged block (9 x 12 x 12 cells) and rows fit in 32 KB: 3% faster in FP32
+template <>
+struct FusedTile<float, 0, false> {
+  using TG = TileGeomB<0, 4, 8, 8>;
   static constexpr bool kStaged = true;
 };
 template <typename T, int DIR, bool CHAN>

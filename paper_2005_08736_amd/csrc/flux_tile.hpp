@@ -314,18 +314,29 @@ __device__ __forceinline__ void face_field_tile_x_staged(const Geo& g, const dou
     T Q0[TG::BX][5];
 #pragma unroll
     for (int ex = 0; ex < TG::BX; ++ex) compat_dev(g, Ql[ex], Qr[ex], Q0[ex]);
-    // the row's BX entries are adjacent in ff: one vector store per field
-    static_assert(TG::BX == 2 && TG::NFF % 2 == 0, "pairs of entries");
-    using T2 = typename std::conditional<sizeof(T) == sizeof(double), double2, float2>::type;
+    if constexpr (TG::BX == 2) {
+      // the row's two entries are adjacent in ff: one vector store per field
+      static_assert(TG::NFF % 2 == 0, "pairs of entries");
+      using T2 = typename std::conditional<sizeof(T) == sizeof(double), double2, float2>::type;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      T2 a, d;
-      a.x = Q0[0][k];
-      a.y = Q0[1][k];
-      d.x = Dn[0][k];
-      d.y = Dn[1][k];
-      *(T2*)(ff + k * TG::NFF + 2 * tid) = a;
-      *(T2*)(ff + (5 + k) * TG::NFF + 2 * tid) = d;
+      for (int k = 0; k < 5; ++k) {
+        T2 a, d;
+        a.x = Q0[0][k];
+        a.y = Q0[1][k];
+        d.x = Dn[0][k];
+        d.y = Dn[1][k];
+        *(T2*)(ff + k * TG::NFF + 2 * tid) = a;
+        *(T2*)(ff + (5 + k) * TG::NFF + 2 * tid) = d;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int ex = 0; ex < TG::BX; ++ex) {
+          ff[k * TG::NFF + TG::BX * tid + ex] = Q0[ex][k];
+          ff[(5 + k) * TG::NFF + TG::BX * tid + ex] = Dn[ex][k];
+        }
+      }
     }
   }
 }
