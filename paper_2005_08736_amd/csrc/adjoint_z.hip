@@ -29,12 +29,12 @@
 
 namespace hgks {
 
-// The flux Jacobian transpose (zflux_jt_columns for the values, zflux_jt_slopes
+// The flux Jacobian transpose (zflux_jt_values for the values, zflux_jt_slopes
 // for the slopes), kept out of line: one copy serves the three face directions.
 template <bool VAR_MU>
-__device__ __noinline__ void zflux_jt_pass(const Geo& g, const double* X, int c0, double dt, const double* Fb,
-                                           const double* dFb, double* Xb) {
-  zflux_jt_columns<VAR_MU>(g, X, c0, dt, Fb, dFb, Xb);
+__device__ __noinline__ void zflux_jt_value_pass(const Geo& g, const double* X, double dt, const double* Fb,
+                                                 const double* dFb, double* Xb) {
+  zflux_jt_values<VAR_MU>(g, X, dt, Fb, dFb, Xb);
 }
 template <bool VAR_MU>
 __device__ __noinline__ void zflux_jt_slope_pass(const Geo& g, const double* X, double dt, const double* Fb,
@@ -165,11 +165,10 @@ __global__ void __launch_bounds__(256) flux_z_vjp_kernel(Geo g, const double* __
         zgp_field<double, DIR, false>(g, ff, ed, kZDl + k, a, t, sm, sl, X[kXDl + k], dum, dum, tok);
         zgp_field<double, DIR, false>(g, ff, ed, kZDr + k, a, t, sm, sl, X[kXDr + k], dum, dum, tok);
       }
-      // input cotangents Xb = J^T (Fb, dFb): tangent passes over the 15 values
-      // (kZTan columns each), the linear side maps for the 45 slopes
+      // input cotangents Xb = J^T (Fb, dFb): one tangent per value column on the
+      // side it moves, the linear side maps for the 45 slopes
       double Xb[kXN];
-#pragma unroll 1
-      for (int c0 = 0; c0 < kXD0; c0 += kZTan) zflux_jt_pass<VAR_MU>(g, X, c0, dt, Fb, dFb, Xb);
+      zflux_jt_value_pass<VAR_MU>(g, X, dt, Fb, dFb, Xb);
       zflux_jt_slope_pass<VAR_MU>(g, X, dt, Fb, dFb, Xb);
       // transpose of the tangential reconstruction, field by field
 #pragma unroll 1

@@ -90,12 +90,109 @@ __host__ __device__ __forceinline__ void zflux_jt_slopes(const Geo& g, const dou
   }
 }
 
-// All 60 entries of J^T (Fb, dFb): tangent passes for the 15 values, the linear
+// The 15 value columns of J^T (Fb, dFb) with one side per column.  A value input
+// moves one Maxwellian (Q0 the equilibrium side, which also enters the Prandtl
+// correction; Q_l, Q_r an initial side) and the collision time, which reaches
+// every side only through its time-integral coefficients, linearly.  So a column
+// runs the side it moves on a forward tangent, and adds the other two sides'
+// moment rows (computed once, in double) times the tangents of their
+// coefficients; begin and end run on the tangent as in zflux_jt_columns.
+template <bool VAR_MU>
+__host__ __device__ __forceinline__ void zflux_jt_values(const Geo& g, const double* X, double dt, const double* Fb,
+                                                         const double* dFb, double* Xb) {
+  using TT = Tan<1>;
+  const double K = g.K;
+  ZCoef<double> c;
+  zflux_begin<VAR_MU>(g, X + kXQ0, X + kXQl, X + kXQr, dt, c);
+  const ZPrim<double>* sp[3] = {&c.s0, &c.sl, &c.sr};
+  double R[3][6][5];
+#pragma unroll 1
+  for (int side = 0; side < 3; ++side) {
+    const int base = side == 0 ? kXD0 : (side == 1 ? kXDl : kXDr);
+    zside_rows(*sp[side], reinterpret_cast<const double(*)[5]>(X + base), side == 0 ? 0 : (side == 1 ? +1 : -1), K,
+               R[side]);
+  }
+  // the primal accumulators of all three sides
+  ZAcc<double> a0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) a0.J1[k] = a0.Jh[k] = a0.I1[k] = a0.Ih[k] = 0.0;
+#pragma unroll 1
+  for (int side = 0; side < 3; ++side) {
+    const double* k1 = side == 0 ? c.eq1 : c.in1;
+    const double* kh = side == 0 ? c.eqh : c.inh;
+    const double rho = sp[side]->rho;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      a0.J1[k] += rho * (k1[0] * R[side][0][k] + k1[1] * R[side][1][k] + k1[2] * R[side][2][k]);
+      a0.Jh[k] += rho * (kh[0] * R[side][0][k] + kh[1] * R[side][1][k] + kh[2] * R[side][2][k]);
+      a0.I1[k] += rho * (k1[0] * R[side][3][k] + k1[1] * R[side][4][k] + k1[2] * R[side][5][k]);
+      a0.Ih[k] += rho * (kh[0] * R[side][3][k] + kh[1] * R[side][4][k] + kh[2] * R[side][5][k]);
+    }
+  }
+#pragma unroll 1
+  for (int i = 0; i < kXD0; ++i) {
+    const int mv = i / 5;  // the side this input moves
+    TT Xt[kXD0];
+#pragma unroll
+    for (int j = 0; j < kXD0; ++j) {
+      Xt[j] = TT(X[j]);
+      Xt[j].d[0] = j == i ? 1.0 : 0.0;
+    }
+    ZCoef<TT> ct;
+    zflux_begin<VAR_MU>(g, Xt + kXQ0, Xt + kXQl, Xt + kXQr, TT(dt), ct);
+    const ZPrim<TT>& st = mv == 0 ? ct.s0 : (mv == 1 ? ct.sl : ct.sr);
+    const int base = mv == 0 ? kXD0 : (mv == 1 ? kXDl : kXDr);
+    TT Dt[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) Dt[d][k] = TT(X[base + 5 * d + k]);
+    ZAcc<TT> am;
+    zside(st, Dt, mv == 0 ? 0 : (mv == 1 ? +1 : -1), TT(K), mv == 0 ? ct.eq1 : ct.in1, mv == 0 ? ct.eqh : ct.inh, am,
+          true);
+    // the accumulators on the tangent: their values the primal sums, their
+    // derivatives the moved side's plus the others' rows times d(coefficients)
+    ZAcc<TT> acc;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      acc.J1[k] = TT(a0.J1[k]);
+      acc.Jh[k] = TT(a0.Jh[k]);
+      acc.I1[k] = TT(a0.I1[k]);
+      acc.Ih[k] = TT(a0.Ih[k]);
+      acc.J1[k].d[0] = am.J1[k].d[0];
+      acc.Jh[k].d[0] = am.Jh[k].d[0];
+      acc.I1[k].d[0] = am.I1[k].d[0];
+      acc.Ih[k].d[0] = am.Ih[k].d[0];
+    }
+#pragma unroll 1
+    for (int side = 0; side < 3; ++side) {
+      if (side == mv) continue;
+      const TT* k1 = side == 0 ? ct.eq1 : ct.in1;
+      const TT* kh = side == 0 ? ct.eqh : ct.inh;
+      const double rho = sp[side]->rho;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        acc.J1[k].d[0] += rho * (k1[0].d[0] * R[side][0][k] + k1[1].d[0] * R[side][1][k] + k1[2].d[0] * R[side][2][k]);
+        acc.Jh[k].d[0] += rho * (kh[0].d[0] * R[side][0][k] + kh[1].d[0] * R[side][1][k] + kh[2].d[0] * R[side][2][k]);
+        acc.I1[k].d[0] += rho * (k1[0].d[0] * R[side][3][k] + k1[1].d[0] * R[side][4][k] + k1[2].d[0] * R[side][5][k]);
+        acc.Ih[k].d[0] += rho * (kh[0].d[0] * R[side][3][k] + kh[1].d[0] * R[side][4][k] + kh[2].d[0] * R[side][5][k]);
+      }
+    }
+    TT F[5], dF[5];
+    zflux_end(g, ct, acc, TT(dt), F, dF);
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sum += Fb[k] * F[k].d[0] + dFb[k] * dF[k].d[0];
+    Xb[i] = sum;
+  }
+}
+
+// All 60 entries of J^T (Fb, dFb): one moved side per value column, the linear
 // side maps for the 45 slopes.
 template <bool VAR_MU>
 __host__ __device__ __forceinline__ void zflux_jt_all(const Geo& g, const double* X, double dt, const double* Fb,
                                                       const double* dFb, double* Xb) {
-  for (int c0 = 0; c0 < kXD0; c0 += kZTan) zflux_jt_columns<VAR_MU>(g, X, c0, dt, Fb, dFb, Xb);
+  zflux_jt_values<VAR_MU>(g, X, dt, Fb, dFb, Xb);
   zflux_jt_slopes<VAR_MU>(g, X, dt, Fb, dFb, Xb);
 }
 

@@ -369,16 +369,11 @@ struct ZAcc {
   T I1[5], J1[5], Ih[5], Jh[5];
 };
 
-// One side of the distribution: its Maxwellian (s), its spatial slopes D[3][5]
-// (local frame, along n, t1, t2), half = 0 (equilibrium, full space), +1 or -1.
-// Adds rho (c0 <u^p psi> + c1 <u^p (a.u) psi> + c2 <u^p A psi>) for p = 1 (I)
-// and p = 0 (J) with the coefficient sets k1 (delta = dt) and kh (dt/2); the
-// time slope A solves <a.u + A> = 0 over the side's full-space Maxwellian.
-// With LIN the term of <psi> (the one part that does not scale with D) is left
-// out: the side's contribution is then linear in D.
+// The moment rows of one side, without rho and the time coefficients: r[0..2]
+// = phi 1, a.u, A for p = 0 (density moments J), r[3..5] the same for p = 1 (flux
+// moments I).  With LIN the phi = 1 rows are zero.
 template <bool LIN = false, typename T>
-__host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* k1,
-                                               const T* kh, ZAcc<T>& acc, bool first) {
+__host__ __device__ __forceinline__ void zside_rows(const ZPrim<T>& s, const T (*D)[5], int half, T K, T (*r)[5]) {
   const T i2l = T(0.5) / s.lam;
   ZGauss<T> G;
   zmom_gauss(G.v, 6, s.V, i2l);
@@ -429,10 +424,33 @@ __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    T j1 = s.rho * (k1[0] * r10[k] + k1[1] * ra0[k] + k1[2] * rA0[k]);
-    T jh = s.rho * (kh[0] * r10[k] + kh[1] * ra0[k] + kh[2] * rA0[k]);
-    T i1 = s.rho * (k1[0] * r11[k] + k1[1] * ra1[k] + k1[2] * rA1[k]);
-    T ih = s.rho * (kh[0] * r11[k] + kh[1] * ra1[k] + kh[2] * rA1[k]);
+    r[0][k] = r10[k];
+    r[1][k] = ra0[k];
+    r[2][k] = rA0[k];
+    r[3][k] = r11[k];
+    r[4][k] = ra1[k];
+    r[5][k] = rA1[k];
+  }
+}
+
+// One side of the distribution: its Maxwellian (s), its spatial slopes D[3][5]
+// (local frame, along n, t1, t2), half = 0 (equilibrium, full space), +1 or -1.
+// Adds rho (c0 <u^p psi> + c1 <u^p (a.u) psi> + c2 <u^p A psi>) for p = 1 (I)
+// and p = 0 (J) with the coefficient sets k1 (delta = dt) and kh (dt/2); the
+// time slope A solves <a.u + A> = 0 over the side's full-space Maxwellian.
+// With LIN the term of <psi> (the one part that does not scale with D) is left
+// out: the side's contribution is then linear in D.
+template <bool LIN = false, typename T>
+__host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* k1,
+                                               const T* kh, ZAcc<T>& acc, bool first) {
+  T r[6][5];
+  zside_rows<LIN>(s, D, half, K, r);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    T j1 = s.rho * (k1[0] * r[0][k] + k1[1] * r[1][k] + k1[2] * r[2][k]);
+    T jh = s.rho * (kh[0] * r[0][k] + kh[1] * r[1][k] + kh[2] * r[2][k]);
+    T i1 = s.rho * (k1[0] * r[3][k] + k1[1] * r[4][k] + k1[2] * r[5][k]);
+    T ih = s.rho * (kh[0] * r[3][k] + kh[1] * r[4][k] + kh[2] * r[5][k]);
     acc.J1[k] = first ? j1 : acc.J1[k] + j1;
     acc.Jh[k] = first ? jh : acc.Jh[k] + jh;
     acc.I1[k] = first ? i1 : acc.I1[k] + i1;
