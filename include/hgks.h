@@ -156,6 +156,25 @@ int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* la
  * Synchronizes the stream. */
 int hgks_diagnostics(hgks_handle* h, double* out);
 
+/* Histogram of the normalized dilatation r = theta / theta_rms over the cells of
+ * the bound state, the quantity whose contours Sec. 3.4 shows for the isotropic
+ * cases (shocklets where r <= -3, strong expansion where r >= 2).  theta = div U
+ * with U = (rho U)/rho by the sixth-order central difference of Sec. 3.1 (wall
+ * ghosts within reach of a wall, as in hgks_diagnostics); theta_rms is the square
+ * root of the mean of theta^2 over the cells (uniform mesh), and r = 0 everywhere
+ * when theta_rms = 0.  nbins uniform bins of width (hi - lo) / nbins cover
+ * [lo, hi): counts (host, nbins + 2 entries) receives in slot 0 the cells with
+ * r < lo, in slot 1 + b those with b = floor((r - lo) * (nbins / (hi - lo))),
+ * clamped to nbins - 1 (the rounding of values just below hi), and in slot
+ * nbins + 1 those with r >= hi or r not finite.  theta_rms (host) receives
+ * theta_rms.  Both evaluate r and the bin in FP64.
+ * Errors: HGKS_E_INVALID_ARG for NULL pointers, nbins outside
+ * [1, HGKS_PDF_MAX_BINS], lo >= hi or lo, hi or hi - lo not finite;
+ * HGKS_E_UNSUPPORTED on a stretched mesh.  Uses the diagnostics' block-partial
+ * workspace; enqueued on the handle's stream, which it synchronizes. */
+#define HGKS_PDF_MAX_BINS 4096
+int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int64_t* counts, double* theta_rms);
+
 /* Per-kernel timing.  While enabled, hgks_step brackets every kernel launch with
  * HIP events recorded on the handle's stream and accumulates the elapsed times
  * per kernel class (see HGKS_KCLASS_*); hgks_step_vjp does the same for its

@@ -50,6 +50,7 @@ def lib():
             "hgks_ref_face_flux": (i32, [P, _D, i32, dbl, _D, _D]),
             "hgks_ref_diagnostics": (i32, [P, _D, _D]),
             "hgks_ref_ndiag": (i32, []),
+            "hgks_ref_dilatation": (i32, [P, _D, _D]),
             "hgks_ref_jvp": (i32, [P, _D, _D, i32, _D, _D, _D]),
             "hgks_ref_count_face_flux": (i32, [P, _D, i32, dbl, _D]),
             "hgks_ref_moments_1d": (i32, [dbl, dbl, _D, _D]),
@@ -166,6 +167,35 @@ def diagnostics(params: dict, q: np.ndarray) -> dict:
     out = np.zeros(NDIAG)
     _check(lib().hgks_ref_diagnostics(ctypes.byref(make_params(params)), _p(q), _p(out)), "diagnostics")
     return dict(zip(DIAG_NAMES, out.tolist()))
+
+
+def dilatation(params: dict, q: np.ndarray) -> np.ndarray:
+    """theta = div U of every cell, shape [nz][ny][nx] (uniform mesh only)."""
+    q = _arr(q)
+    th = np.zeros(q.shape[1:])
+    _check(lib().hgks_ref_dilatation(ctypes.byref(make_params(params)), _p(q), _p(th)), "dilatation")
+    return th
+
+
+def dilatation_pdf(params: dict, q: np.ndarray, nbins: int, lo: float, hi: float):
+    """Histogram of r = theta / theta_rms (Sec. 3.4's normalized dilation), with
+    theta_rms the root mean square of theta over the cells and r = 0 where it is
+    zero.  Returns (counts, theta_rms, r): counts has nbins + 2 slots, slot 0 for
+    r < lo, 1 + floor((r - lo) * (nbins / (hi - lo))) (at most nbins) inside
+    [lo, hi), nbins + 1 for r >= hi or r not finite.  Plain numpy, FP64."""
+    th = dilatation(params, q).ravel()
+    rms = float(np.sqrt(np.mean(th * th)))
+    r = th / rms if rms > 0.0 else np.zeros_like(th)
+    scale = float(nbins) / (hi - lo)
+    slot = np.empty(r.size, dtype=np.int64)
+    below = r < lo
+    above = ~below & ((r >= hi) | ~np.isfinite(r))
+    inside = ~below & ~above
+    slot[below] = 0
+    slot[above] = nbins + 1
+    slot[inside] = 1 + np.minimum(np.floor((r[inside] - lo) * scale).astype(np.int64), nbins - 1)
+    counts = np.bincount(slot, minlength=nbins + 2).astype(np.int64)
+    return counts, rms, r.reshape(q.shape[1:])
 
 
 def jvp(params: dict, q: np.ndarray, dq: np.ndarray, dts):

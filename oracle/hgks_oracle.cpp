@@ -981,6 +981,36 @@ static void step(Box<R>& b, const R& dt) {
 }
 
 // ---------------------------------------------------------------------------
+// Dilatation theta = div U of every cell (the quantity whose normalized form
+// theta / theta_rms Sec. 3.4 draws for the isotropic cases), U = m/rho, with the
+// sixth-order central difference (-1, 9, -45, 45, -9, 1)/(60 h) of Sec. 3.1 along
+// each axis, written as sum_o w_o (U(+o) - U(-o)) with w = (45, -9, 1) so that a
+// constant field gives exactly zero, as the derivative of a constant is; ghost
+// cells as in the step (periodic wrap, wall mirrors).  Uniform axes only.  theta
+// is written in the state's cell order (x fastest).
+// ---------------------------------------------------------------------------
+static void dilatation(Box<double>& b, double* theta) {
+  fill_ghosts(b);
+  const double w[4] = {0.0, 45.0, -9.0, 1.0};
+  for (int k = 0; k < b.n[2]; ++k)
+    for (int j = 0; j < b.n[1]; ++j)
+      for (int i = 0; i < b.n[0]; ++i) {
+        double th = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          auto U = [&](int off) {
+            int ii = i, jj = j, kk = k;
+            if (a == 0) ii += off; else if (a == 1) jj += off; else kk += off;
+            return b.at(1 + a, ii, jj, kk) / b.at(0, ii, jj, kk);
+          };
+          double sum = 0.0;
+          for (int o = 1; o <= 3; ++o) sum += w[o] * (U(o) - U(-o));
+          th += sum / (60.0 * b.h[a]);
+        }
+        theta[((long long)k * b.n[1] + j) * b.n[0] + i] = th;
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics (Sec. 3.1 and 3.4).  Point values are cell averages, U = m/rho;
 // spatial derivatives by the sixth-order central difference
 // (-1, 9, -45, 45, -9, 1)/(60 h) of Sec. 3.1 (uniform axes only).
@@ -1233,6 +1263,15 @@ int hgks_ref_diagnostics(const ref_params* p, const double* q, double* out) {
   ref::Box<double> b(*p);
   b.load(q);
   ref::diagnostics(b, out);
+  return 0;
+}
+
+int hgks_ref_dilatation(const ref_params* p, const double* q, double* theta) {
+  if (ref::validate(p)) return -1;
+  ref::Box<double> b(*p);
+  if (b.stretched) return -1;
+  b.load(q);
+  ref::dilatation(b, theta);
   return 0;
 }
 

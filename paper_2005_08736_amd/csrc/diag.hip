@@ -200,6 +200,126 @@ __global__ void diag_final_kernel(const double* __restrict__ part, double* __res
 
 size_t diag_partial_doubles() { return size_t(kDiagBlocks) * kNDiag; }
 
+// ---- normalized dilatation theta / theta_rms (Sec. 3.4, the dilation contours
+// of the isotropic cases: shocklets where it is at most -3, strong expansion where
+// it is at least 2).  theta = div U by the same sixth-order central difference as
+// the diagnostics, recomputed in both passes rather than stored.  The partial
+// buffer holds the block sums of theta^2 in its first kDiagBlocks entries,
+// theta_rms at kDiagBlocks, then the nbins + 2 counts as 64-bit integers.
+static_assert(size_t(kDiagBlocks) + 1 + kPdfMaxBins + 2 <= size_t(kDiagBlocks) * kNDiag,
+              "the counts fit in the partial buffer");
+
+__device__ __forceinline__ double dilatation_at(const Geo& g, const double* __restrict__ q, long long idx,
+                                                const int* c) {
+  const double c6[3] = {45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0};
+  double th = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const long long base = idx - (long long)c[a] * g.stride[a];
+    double s = 0.0;
+#pragma unroll
+    for (int o = 1; o <= 3; ++o) {
+      if (a == 1 && g.wall_y && (c[1] - o < 0 || c[1] + o >= g.n[1])) {
+        double Qp[5], Qm[5];
+        load_cell_wall(g, q, c[0], c[1] + o, c[2], Qp);
+        load_cell_wall(g, q, c[0], c[1] - o, c[2], Qm);
+        s += c6[o - 1] * (Qp[1 + a] / Qp[0] - Qm[1 + a] / Qm[0]);
+        continue;
+      }
+      const long long ip = base + (long long)wrapi(c[a] + o, g.n[a]) * g.stride[a];
+      const long long im = base + (long long)wrapi(c[a] - o, g.n[a]) * g.stride[a];
+      s += c6[o - 1] * (q[(long long)(1 + a) * g.N + ip] / q[ip] - q[(long long)(1 + a) * g.N + im] / q[im]);
+    }
+    th += s * g.inv_h[a];
+  }
+  return th;
+}
+
+__device__ __forceinline__ void cell_coords(const Geo& g, long long idx, int* c) {
+  c[0] = int(idx % g.n[0]);
+  const long long r = idx / g.n[0];
+  c[1] = int(r % g.n[1]);
+  c[2] = int(r / g.n[1]);
+}
+
+// block sums of theta^2 in a fixed order
+__global__ void __launch_bounds__(kDiagThreads) dil_sum_kernel(Geo g, const double* __restrict__ q,
+                                                               double* __restrict__ part) {
+  __shared__ double red[kDiagThreads];
+  double acc = 0.0;
+  for (long long idx = (long long)blockIdx.x * kDiagThreads + threadIdx.x; idx < g.N;
+       idx += (long long)kDiagBlocks * kDiagThreads) {
+    int c[3];
+    cell_coords(g, idx, c);
+    const double th = dilatation_at(g, q, idx, c);
+    acc += th * th;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// theta_rms from the block sums (serial), and the global counts cleared
+__global__ void dil_rms_kernel(Geo g, double* __restrict__ part, int nslots) {
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(part + kDiagBlocks + 1);
+  for (int i = threadIdx.x; i < nslots; i += blockDim.x) counts[i] = 0ull;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < kDiagBlocks; ++b) s += part[b];
+    part[kDiagBlocks] = sqrt(s / double(g.N));
+  }
+}
+
+// histogram of r = theta / theta_rms (r = 0 where theta_rms = 0, i.e. every theta
+// is zero): slot 0 for r < lo, 1 + floor((r - lo) * scale) for lo <= r < hi (the
+// last bin also takes the rounding of values just below hi), nbins + 1 for r >= hi
+// and for non-finite r.  Counts are integers, so their order of addition is
+// immaterial.
+__global__ void __launch_bounds__(kDiagThreads) dil_hist_kernel(Geo g, const double* __restrict__ q,
+                                                                double* __restrict__ part, int nbins, double lo,
+                                                                double hi, double scale) {
+  __shared__ unsigned int hist[kPdfMaxBins + 2];
+  const int nslots = nbins + 2;
+  for (int i = threadIdx.x; i < nslots; i += kDiagThreads) hist[i] = 0u;
+  __syncthreads();
+  const double rms = part[kDiagBlocks];
+  for (long long idx = (long long)blockIdx.x * kDiagThreads + threadIdx.x; idx < g.N;
+       idx += (long long)kDiagBlocks * kDiagThreads) {
+    int c[3];
+    cell_coords(g, idx, c);
+    const double th = dilatation_at(g, q, idx, c);
+    const double r = rms > 0.0 ? th / rms : 0.0;
+    int slot;
+    if (r < lo) {
+      slot = 0;
+    } else if (r >= hi || !(r == r)) {
+      slot = nbins + 1;
+    } else {
+      const int b = int(floor((r - lo) * scale));
+      slot = 1 + (b < nbins - 1 ? b : nbins - 1);
+    }
+    atomicAdd(&hist[slot], 1u);
+  }
+  __syncthreads();
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(part + kDiagBlocks + 1);
+  for (int i = threadIdx.x; i < nslots; i += kDiagThreads)
+    if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
+}
+
+void launch_dilatation_pdf(const Geo& g, const double* q, double* part, int nbins, double lo, double hi,
+                           hipStream_t st) {
+  dil_sum_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part);
+  dil_rms_kernel<<<1, 256, 0, st>>>(g, part, nbins + 2);
+  dil_hist_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part, nbins, lo, hi, double(nbins) / (hi - lo));
+}
+
+size_t dilatation_pdf_rms_offset() { return kDiagBlocks; }
+size_t dilatation_pdf_counts_offset() { return kDiagBlocks + 1; }
+
 void launch_diagnostics(const Geo& g, const double* q, double* part, double* out, hipStream_t st) {
   diag_partial_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part, 0, out);
   diag_final_kernel<<<1, 64, 0, st>>>(part, out, 0, 1.0);

@@ -464,6 +464,23 @@ int hgks_diagnostics(hgks_handle* h, double* out) {
   return hip_status(hipStreamSynchronize(h->stream));
 }
 
+static_assert(HGKS_PDF_MAX_BINS == kPdfMaxBins, "one bin limit");
+
+int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int64_t* counts, double* theta_rms) {
+  if (!h || !counts || !theta_rms || nbins < 1 || nbins > HGKS_PDF_MAX_BINS) return HGKS_E_INVALID_ARG;
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi) || !std::isfinite(hi - lo)) return HGKS_E_INVALID_ARG;
+  if (h->geo.stretch_y) return HGKS_E_UNSUPPORTED;
+  launch_dilatation_pdf(h->geo, h->q, h->diag_part, nbins, lo, hi, h->stream);
+  if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(theta_rms, h->diag_part + dilatation_pdf_rms_offset(), sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(counts, h->diag_part + dilatation_pdf_counts_offset(), sizeof(int64_t) * size_t(nbins + 2),
+                     hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  return hip_status(hipStreamSynchronize(h->stream));
+}
+
 int hgks_profile_enable(hgks_handle* h, int enable) {
   if (!h) return HGKS_E_INVALID_ARG;
   if (!enable) {

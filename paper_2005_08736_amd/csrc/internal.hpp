@@ -37,5 +37,11 @@ void launch_set_dt(Ctrl* ctrl, double dt, hipStream_t st);
 void launch_copy(const double* src, double* dst, long long n, hipStream_t st);
 void launch_diagnostics(const Geo& g, const double* q, double* part, double* out, hipStream_t st);
 size_t diag_partial_doubles();
+// histogram of the normalized dilatation, in the diagnostics' partial buffer
+constexpr int kPdfMaxBins = 4096;
+void launch_dilatation_pdf(const Geo& g, const double* q, double* part, int nbins, double lo, double hi,
+                           hipStream_t st);
+size_t dilatation_pdf_rms_offset();
+size_t dilatation_pdf_counts_offset();
 
 }  // namespace hgks

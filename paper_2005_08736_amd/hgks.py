@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,8 +37,9 @@ DIAG_NAMES = [
 EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
-    "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp",
+    "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp", "hgks_dilatation_pdf",
 ]
+PDF_MAX_BINS = 4096
 KCLASS_NAMES = ["dt", "flux_stage1", "flux_stage2", "stage1", "stage2", "operator_vjp"]
 
 
@@ -97,6 +99,8 @@ def load():
     L.hgks_profile_read.argtypes = [vp, D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     L.hgks_step_vjp.restype = ctypes.c_int
     L.hgks_step_vjp.argtypes = [vp, vp, dbl, vp, vp]
+    L.hgks_dilatation_pdf.restype = ctypes.c_int
+    L.hgks_dilatation_pdf.argtypes = [vp, ctypes.c_int32, dbl, dbl, ctypes.POINTER(ctypes.c_int64), D]
     L.hgks_strerror.restype = ctypes.c_char_p
     L.hgks_strerror.argtypes = [ctypes.c_int]
     _lib = L
@@ -190,6 +194,19 @@ class Solver:
         out = (ctypes.c_double * HGKS_NDIAG)()
         _check(load().hgks_diagnostics(self._h, out), "hgks_diagnostics")
         return dict(zip(DIAG_NAMES, list(out)))
+
+    def dilatation_pdf(self, nbins: int, lo: float, hi: float):
+        """Histogram of theta / theta_rms (hgks_dilatation_pdf): returns (counts,
+        theta_rms), counts an int64 array of nbins + 2 (below lo, the bins, at or
+        above hi)."""
+        if not 1 <= int(nbins) <= PDF_MAX_BINS:
+            raise ValueError(f"nbins must lie in [1, {PDF_MAX_BINS}]")
+        counts = np.zeros(int(nbins) + 2, dtype=np.int64)
+        rms = ctypes.c_double(0.0)
+        _check(load().hgks_dilatation_pdf(self._h, int(nbins), float(lo), float(hi),
+                                          counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(rms)),
+               "hgks_dilatation_pdf")
+        return counts, rms.value
 
     def profile(self, enable: bool = True):
         _check(load().hgks_profile_enable(self._h, int(bool(enable))), "hgks_profile_enable")
