@@ -175,6 +175,23 @@ int hgks_diagnostics(hgks_handle* h, double* out);
 #define HGKS_PDF_MAX_BINS 4096
 int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int64_t* counts, double* theta_rms);
 
+/* Plane-averaged profiles of the bound state per y row, the statistics of the
+ * channel in Sec. 3.3 (mean velocity, velocity fluctuations, Reynolds stress, and
+ * the total-stress balance built from them): Reynolds averages <.> over the
+ * nx * nz cells of each row, with U = (rho U)/rho, p = (gamma - 1)(rho E -
+ * rho |U|^2 / 2) and T = p / rho per cell, the second moments about the row
+ * means (u' = U - <U>).  out (host, ny * HGKS_NPROFILE doubles, row j at
+ * out + j * HGKS_NPROFILE) receives
+ *   0 <rho>, 1 <U>, 2 <V>, 3 <W>, 4 <p>, 5 <T>, 6 <u'u'>, 7 <v'v'>, 8 <w'w'>,
+ *   9 <u'v'>, 10 <rho U>.
+ * Any mesh and boundary.  Fixed reduction order, so repeated calls are bitwise
+ * identical.  Uses the face-flux arrays of the workspace as scratch (like
+ * hgks_step_vjp, so they no longer hold the step's face fluxes afterwards);
+ * enqueued on the handle's stream, which it synchronizes.  Errors:
+ * HGKS_E_INVALID_ARG for NULL pointers, HGKS_E_DEVICE. */
+#define HGKS_NPROFILE 11
+int hgks_plane_profiles(hgks_handle* h, double* out);
+
 /* Per-kernel timing.  While enabled, hgks_step brackets every kernel launch with
  * HIP events recorded on the handle's stream and accumulates the elapsed times
  * per kernel class (see HGKS_KCLASS_*); hgks_step_vjp does the same for its

@@ -198,6 +198,32 @@ def dilatation_pdf(params: dict, q: np.ndarray, nbins: int, lo: float, hi: float
     return counts, rms, r.reshape(q.shape[1:])
 
 
+PROFILE_NAMES = ["rho", "U", "V", "W", "p", "T", "uu", "vv", "ww", "uv", "rhoU"]
+
+
+def plane_profiles(params: dict, q: np.ndarray) -> np.ndarray:
+    """Reynolds averages over the x-z plane of each y row (the channel statistics of
+    Sec. 3.3): <rho>, <U>, <V>, <W>, <p>, <T>, <u'u'>, <v'v'>, <w'w'>, <u'v'>,
+    <rho U> per row, U = (rho U)/rho, p = (gamma - 1)(rho E - rho |U|^2/2),
+    T = p/rho, fluctuations about the row means.  Plain numpy, FP64; [ny, 11]."""
+    q = _arr(q)
+    rho = q[0]
+    U, V, W = q[1] / rho, q[2] / rho, q[3] / rho
+    p = (params["gamma"] - 1.0) * (q[4] - 0.5 * rho * (U * U + V * V + W * W))
+    T = p / rho
+
+    def row_mean(a):
+        return a.mean(axis=(0, 2))
+
+    Um, Vm, Wm = row_mean(U), row_mean(V), row_mean(W)
+    du = U - Um[None, :, None]
+    dv = V - Vm[None, :, None]
+    dw = W - Wm[None, :, None]
+    cols = [row_mean(rho), Um, Vm, Wm, row_mean(p), row_mean(T), row_mean(du * du), row_mean(dv * dv),
+            row_mean(dw * dw), row_mean(du * dv), row_mean(rho * U)]
+    return np.stack(cols, axis=1)
+
+
 def jvp(params: dict, q: np.ndarray, dq: np.ndarray, dts):
     q = _arr(q)
     dq = _arr(dq)

@@ -317,6 +317,82 @@ void launch_dilatation_pdf(const Geo& g, const double* q, double* part, int nbin
   dil_hist_kernel<<<kDiagBlocks, kDiagThreads, 0, st>>>(g, q, part, nbins, lo, hi, double(nbins) / (hi - lo));
 }
 
+// ---- plane-averaged profiles per y row (Sec. 3.3: mean velocity, velocity
+// fluctuations and Reynolds stress of the channel).  One block per row; Reynolds
+// averages over the row's nx * nz cells, the second moments about the row means
+// in a second pass over the row.  Fixed reduction order.
+constexpr int kProfThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kProfThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ void row_cell(const Geo& g, const double* __restrict__ q, int j, long long m, double& rho,
+                                         double* U, double& p) {
+  const int x = int(m % g.n[0]);
+  const long long z = m / g.n[0];
+  const long long idx = (long long)x + (long long)j * g.stride[1] + z * g.stride[2];
+  rho = q[idx];
+  const double ir = 1.0 / rho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = q[(long long)(1 + k) * g.N + idx] * ir;
+  const double u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+  p = g.gm1 * (q[4 * g.N + idx] - 0.5 * rho * u2);
+}
+
+__global__ void __launch_bounds__(kProfThreads) profile_kernel(Geo g, const double* __restrict__ q,
+                                                               double* __restrict__ out) {
+  __shared__ double red[kProfThreads];
+  const int j = blockIdx.x;
+  const long long nxz = (long long)g.n[0] * g.n[2];
+  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // rho, U, V, W, p, T, rho U
+  for (long long m = threadIdx.x; m < nxz; m += kProfThreads) {
+    double rho, U[3], p;
+    row_cell(g, q, j, m, rho, U, p);
+    s[0] += rho;
+    s[1] += U[0];
+    s[2] += U[1];
+    s[3] += U[2];
+    s[4] += p;
+    s[5] += p / rho;
+    s[6] += rho * U[0];
+  }
+  double mean[7];
+#pragma unroll 1
+  for (int k = 0; k < 7; ++k) mean[k] = block_sum(s[k], red) / double(nxz);
+  double c[4] = {0.0, 0.0, 0.0, 0.0};  // u'u', v'v', w'w', u'v'
+  for (long long m = threadIdx.x; m < nxz; m += kProfThreads) {
+    double rho, U[3], p;
+    row_cell(g, q, j, m, rho, U, p);
+    const double du = U[0] - mean[1], dv = U[1] - mean[2], dw = U[2] - mean[3];
+    c[0] += du * du;
+    c[1] += dv * dv;
+    c[2] += dw * dw;
+    c[3] += du * dv;
+  }
+  double cov[4];
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) cov[k] = block_sum(c[k], red) / double(nxz);
+  if (threadIdx.x == 0) {
+    double* o = out + (long long)j * kNProfile;
+    for (int k = 0; k < 6; ++k) o[k] = mean[k];
+    for (int k = 0; k < 4; ++k) o[6 + k] = cov[k];
+    o[10] = mean[6];
+  }
+}
+
+void launch_plane_profiles(const Geo& g, const double* q, double* out, hipStream_t st) {
+  profile_kernel<<<g.n[1], kProfThreads, 0, st>>>(g, q, out);
+}
+
 size_t dilatation_pdf_rms_offset() { return kDiagBlocks; }
 size_t dilatation_pdf_counts_offset() { return kDiagBlocks + 1; }
 

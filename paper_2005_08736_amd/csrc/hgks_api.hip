@@ -481,6 +481,20 @@ int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int
   return hip_status(hipStreamSynchronize(h->stream));
 }
 
+static_assert(HGKS_NPROFILE == kNProfile, "one profile width");
+
+int hgks_plane_profiles(hgks_handle* h, double* out) {
+  if (!h || !out) return HGKS_E_INVALID_ARG;
+  // ny rows of kNProfile doubles; the face-flux arrays hold at least 15 N >= 540 ny doubles
+  double* scratch = reinterpret_cast<double*>(h->fl);
+  launch_plane_profiles(h->geo, h->q, scratch, h->stream);
+  if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(out, scratch, sizeof(double) * size_t(kNProfile) * size_t(h->geo.n[1]), hipMemcpyDeviceToHost,
+                     h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  return hip_status(hipStreamSynchronize(h->stream));
+}
+
 int hgks_profile_enable(hgks_handle* h, int enable) {
   if (!h) return HGKS_E_INVALID_ARG;
   if (!enable) {

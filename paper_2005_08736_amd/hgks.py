@@ -38,8 +38,10 @@ EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
     "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp", "hgks_dilatation_pdf",
+    "hgks_plane_profiles",
 ]
 PDF_MAX_BINS = 4096
+PROFILE_NAMES = ["rho", "U", "V", "W", "p", "T", "uu", "vv", "ww", "uv", "rhoU"]
 KCLASS_NAMES = ["dt", "flux_stage1", "flux_stage2", "stage1", "stage2", "operator_vjp"]
 
 
@@ -101,6 +103,8 @@ def load():
     L.hgks_step_vjp.argtypes = [vp, vp, dbl, vp, vp]
     L.hgks_dilatation_pdf.restype = ctypes.c_int
     L.hgks_dilatation_pdf.argtypes = [vp, ctypes.c_int32, dbl, dbl, ctypes.POINTER(ctypes.c_int64), D]
+    L.hgks_plane_profiles.restype = ctypes.c_int
+    L.hgks_plane_profiles.argtypes = [vp, D]
     L.hgks_strerror.restype = ctypes.c_char_p
     L.hgks_strerror.argtypes = [ctypes.c_int]
     _lib = L
@@ -207,6 +211,15 @@ class Solver:
                                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(rms)),
                "hgks_dilatation_pdf")
         return counts, rms.value
+
+    def plane_profiles(self) -> np.ndarray:
+        """Per-y-row plane averages (hgks_plane_profiles): array [ny, 11], columns
+        as PROFILE_NAMES."""
+        ny = self.params["ny"]
+        out = np.zeros((ny, len(PROFILE_NAMES)))
+        _check(load().hgks_plane_profiles(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "hgks_plane_profiles")
+        return out
 
     def profile(self, enable: bool = True):
         _check(load().hgks_profile_enable(self._h, int(bool(enable))), "hgks_profile_enable")
