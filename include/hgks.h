@@ -83,6 +83,12 @@ typedef struct {
                                   (Sec. 3.3): (rho U) += dt/2 (rho^{n+1} + rho^n) f_x,
                                   (rho E) += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x */
   int32_t precision;       /* HGKS_PREC_* */
+  double bulk_momentum;    /* 0: off.  > 0: constant bulk momentum (Sec. 3.3): each step's
+                              force f_x, applied by the same trapezoidal rule, is the value
+                              that makes the box integral of (rho U)^{n+1} equal
+                              bulk_momentum |Omega|, i.e. f_x = (bulk_momentum |Omega| -
+                              int (rho U)~ dOmega) / (dt/2 int (rho^n + rho~) dOmega) with ~
+                              the unforced update; excludes body_force_x != 0 */
 } hgks_params;
 
 typedef struct hgks_handle hgks_handle;

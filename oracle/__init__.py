@@ -24,6 +24,7 @@ PARAM_FIELDS = [
     ("mode", ctypes.c_int32), ("cfl", ctypes.c_double),
     ("c_art", ctypes.c_double), ("weno_eps", ctypes.c_double), ("weno_p", ctypes.c_int32),
     ("T_wall", ctypes.c_double), ("body_force_x", ctypes.c_double),
+    ("bulk_momentum", ctypes.c_double),
 ]
 
 
@@ -86,7 +87,8 @@ def _arr(x, n=None):
 def make_params(d: dict) -> RefParams:
     p = RefParams()
     for name, _ in PARAM_FIELDS:
-        setattr(p, name, d[name])
+        # the constant-bulk-momentum switch is off unless given
+        setattr(p, name, d.get(name, 0.0) if name == "bulk_momentum" else d[name])
     return p
 
 

@@ -92,6 +92,7 @@ extern "C" typedef struct {
   double c_art, weno_eps;
   int32_t weno_p;
   double T_wall, body_force_x;
+  double bulk_momentum;  // > 0: constant bulk momentum (Sec. 3.3), target mean of rho U over the box
 } ref_params;
 
 // ---------------------------------------------------------------------------
@@ -945,8 +946,10 @@ static bool physical(const Box<R>& b) {
 // One two-stage fourth-order step (Eq. (two-stage)):
 //   Q*      = Q^n + dt/2 L(Q^n) + dt^2/8 dL(Q^n)
 //   Q^{n+1} = Q^n + dt L(Q^n) + dt^2/6 (dL(Q^n) + 2 dL(Q*))
-// followed, for the channel, by the constant body force of Sec. 3.3:
-//   (rho U)^{n+1} += dt/2 (rho^{n+1} + rho^n) f_x,  (rho E)^{n+1} += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x.
+// followed, for the channel, by the body force of Sec. 3.3:
+//   (rho U)^{n+1} += dt/2 (rho^{n+1} + rho^n) f_x,  (rho E)^{n+1} += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x,
+// with f_x the constant body_force_x, or, with bulk_momentum > 0, the value that
+// makes the box integral of (rho U)^{n+1} equal bulk_momentum |Omega|.
 template <class R>
 static void step(Box<R>& b, const R& dt) {
   std::vector<R> L1, dL1, L2, dL2;
@@ -967,8 +970,24 @@ static void step(Box<R>& b, const R& dt) {
           size_t o = b.idx(c, i, j, k);
           b.q[o] = qn[o] + dt * L1[o] + dt * dt / R(6.0) * (dL1[o] + R(2.0) * dL2[o]);
         }
-  if (b.P.body_force_x != 0.0) {
-    const R fx = R(b.P.body_force_x);
+  if (b.P.body_force_x != 0.0 || b.P.bulk_momentum > 0.0) {
+    R fx = R(b.P.body_force_x);
+    if (b.P.bulk_momentum > 0.0) {
+      // constant bulk momentum (Sec. 3.3): the force that brings the integral of
+      // rho U over the box from its unforced value to bulk_momentum |Omega|,
+      // f_x = (M* - int (rho U)~ dOmega) / (dt 1/2 int (rho^n + rho~) dOmega)
+      R M(0.0), S(0.0);
+      double vol = 0.0;
+      for (int k = 0; k < b.n[2]; ++k)
+        for (int j = 0; j < b.n[1]; ++j)
+          for (int i = 0; i < b.n[0]; ++i) {
+            const double V = b.cell_volume(j);
+            M = M + b.q[b.idx(1, i, j, k)] * R(V);
+            S = S + (qn[b.idx(0, i, j, k)] + b.q[b.idx(0, i, j, k)]) * R(V);
+            vol += V;
+          }
+      fx = (R(b.P.bulk_momentum * vol) - M) / (dt * R(0.5) * S);
+    }
     for (int k = 0; k < b.n[2]; ++k)
       for (int j = 0; j < b.n[1]; ++j)
         for (int i = 0; i < b.n[0]; ++i) {
@@ -1168,6 +1187,7 @@ static int validate(const ref_params* p) {
   if (!(p->gamma > 1.0) || !(p->prandtl > 0.0) || !(p->mu_ref >= 0.0) || !(p->cfl > 0.0)) return -1;
   if (p->mode != 0 && p->mode != 1) return -1;
   if (p->bc_y != 0 && p->bc_y != 1) return -1;
+  if (!(p->bulk_momentum >= 0.0) || (p->bulk_momentum > 0.0 && p->body_force_x != 0.0)) return -1;
   return 0;
 }
 

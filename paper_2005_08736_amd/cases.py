@@ -31,7 +31,7 @@ PARAM_DEFAULTS = dict(
     mu_ref=1.0 / 1600.0, T_ref=1.0, mu_exp=0.0,
     mode=0, cfl=0.4,
     c_art=1.0, weno_eps=1e-6, weno_p=2,
-    T_wall=1.0, body_force_x=0.0,
+    T_wall=1.0, body_force_x=0.0, bulk_momentum=0.0,
 )
 
 

@@ -28,6 +28,7 @@ struct hgks_handle {
   double* diag_out;     // derived diagnostics [HGKS_NDIAG]
   double* speed_part;   // block maxima of the CFL speed
   double* lam_star;     // adjoint of Q* (step adjoint)
+  double* mflux;        // constant bulk momentum: stage-2 block sums, then the step's force
   long long steps_done; // steps advanced over the handle's lifetime
   int failed_step;
   // optional per-kernel timing
@@ -45,7 +46,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, lam_star, ymet, fwall, total;
+  size_t ctrl, qs, rr, fl, diag_part, diag_out, speed_part, lam_star, ymet, fwall, mflux, total;
 };
 
 Layout layout_for(const hgks_params* p) {
@@ -69,6 +70,8 @@ Layout layout_for(const hgks_params* p) {
   // channel: metric tables of the stretched y mesh, fluxes of the bottom wall faces
   L.ymet = take(p->stretch_b > 0.0 ? sizeof(double) * (size_t(kYmTableDoubles) * p->ny + 1) : 0);
   L.fwall = take(p->bc_y == HGKS_BC_WALL_ISOTHERMAL ? tf * 10 * size_t(p->nx) * p->nz : 0);
+  // constant bulk momentum: three block sums per stage-2 block, then the force
+  L.mflux = take(p->bulk_momentum > 0.0 ? sizeof(double) * (3 * size_t((N + 255) / 256) + 1) : 0);
   L.total = off;
   return L;
 }
@@ -116,6 +119,8 @@ int validate(const hgks_params* p) {
     if (!(p->weno_eps > 0.0) || p->weno_p < 1 || p->weno_p > 4 || !(p->c_art >= 0.0)) return HGKS_E_INVALID_ARG;
   }
   if (!(p->stretch_b >= 0.0)) return HGKS_E_INVALID_ARG;
+  if (!(p->bulk_momentum >= 0.0) || !std::isfinite(p->bulk_momentum)) return HGKS_E_INVALID_ARG;
+  if (p->bulk_momentum > 0.0 && p->body_force_x != 0.0) return HGKS_E_INVALID_ARG;
   if (p->bc_y == HGKS_BC_WALL_ISOTHERMAL && !(p->T_wall > 0.0)) return HGKS_E_INVALID_ARG;
   // the stretched mesh is the channel's wall-normal mesh; walls and stretching
   // are implemented for the smooth mode
@@ -254,10 +259,16 @@ void stage1(hgks_handle* h, const double* cur, double* other, int step) {
 }
 
 void stage2(hgks_handle* h, const double* cur, double* other, int step) {
+  // with constant bulk momentum the stage-2 kernel leaves the force out and writes
+  // block sums instead of speed maxima; the force kernels finish the step
   if (f32(h))
-    launch_stage2(h->geo, h->rr, fl_dir<float>(h, 0), cur, other, h->ctrl, h->speed_part, step, h->stream);
+    launch_stage2(h->geo, h->rr, fl_dir<float>(h, 0), cur, other, h->ctrl, h->speed_part, h->mflux, step,
+                  h->stream);
   else
-    launch_stage2(h->geo, h->rr, fl_dir<double>(h, 0), cur, other, h->ctrl, h->speed_part, step, h->stream);
+    launch_stage2(h->geo, h->rr, fl_dir<double>(h, 0), cur, other, h->ctrl, h->speed_part, h->mflux, step,
+                  h->stream);
+  if (h->mflux) launch_bulk_force(h->geo, cur, other, h->ctrl, h->mflux, h->p.bulk_momentum, h->speed_part, step,
+                                  h->stream);
 }
 
 }  // namespace
@@ -299,6 +310,7 @@ int hgks_init(const hgks_params* p, double* q, void* workspace, size_t ws_bytes,
   h->lam_star = reinterpret_cast<double*>(h->ws + L.lam_star);
   if (h->geo.stretch_y) h->geo.ym = reinterpret_cast<const double*>(h->ws + L.ymet);
   if (h->geo.wall_y) h->geo.fwall = h->ws + L.fwall;
+  h->mflux = p->bulk_momentum > 0.0 ? reinterpret_cast<double*>(h->ws + L.mflux) : nullptr;
   h->steps_done = 0;
   h->failed_step = -1;
   h->profiling = false;
@@ -432,7 +444,7 @@ int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, d
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n) {
   if (!h || !q_n || !lam_np1 || !lam_n || !(dt > 0.0)) return HGKS_E_INVALID_ARG;
   if (lam_n == lam_np1 || lam_n == q_n) return HGKS_E_INVALID_ARG;
-  if (h->geo.wall_y || h->geo.stretch_y || h->geo.fx != 0.0) return HGKS_E_UNSUPPORTED;
+  if (h->geo.wall_y || h->geo.stretch_y || h->geo.fx != 0.0 || h->mflux) return HGKS_E_UNSUPPORTED;
   // smooth mode: constant viscosity, FP64 or the FP32-flux form; mode Z: FP64
   if (h->p.mode == HGKS_MODE_SMOOTH && h->p.mu_exp != 0.0) return HGKS_E_UNSUPPORTED;
   if (h->p.mode == HGKS_MODE_WENOZ && f32(h)) return HGKS_E_UNSUPPORTED;

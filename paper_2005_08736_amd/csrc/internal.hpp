@@ -11,7 +11,11 @@ void launch_stage1(const Geo& g, const double* qn, const TF* fl, double* qs, dou
                    hipStream_t st);
 template <typename TF>
 void launch_stage2(const Geo& g, const double* rr, const TF* fl, const double* qn, double* qout, Ctrl* ctrl,
-                   double* part, int step, hipStream_t st);
+                   double* part, double* mpart, int step, hipStream_t st);
+// constant bulk momentum: the force from the stage-2 block sums in mflux, then
+// applied to qout with the CFL block maxima
+void launch_bulk_force(const Geo& g, const double* qn, double* qout, Ctrl* ctrl, double* mflux, double m_b,
+                       double* part, int step, hipStream_t st);
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st);
 size_t speed_partials(const Geo& g);
 void launch_reset_ctrl(Ctrl* ctrl, hipStream_t st);

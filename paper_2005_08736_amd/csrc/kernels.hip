@@ -182,19 +182,48 @@ __global__ void __launch_bounds__(256) stage1_kernel(Geo g, const double* __rest
   }
 }
 
+// fixed-order sums of three values over a 256-thread block, left in out[0..2]
+// (LDS or global) by thread 0
+__device__ __forceinline__ void block_sums3(double a, double b, double c, double* out) {
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+  }
+}
+
+__device__ __forceinline__ double cell_volume(const Geo& g, int j) {
+  return g.h[0] * g.h[2] * (g.stretch_y ? ym_dy(g, j) : g.h[1]);
+}
+
 // Q^{n+1} = R + dt^2/3 dL(Q*); then the channel's constant body force f_x
 // (Sec. 3.3), with the trapezoidal rule over the step:
 //   (rho U)^{n+1} += dt/2 (rho^{n+1} + rho^n) f_x,
 //   (rho E)^{n+1} += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x;
-// block maxima of the next step's CFL speed.
-template <typename TF>
+// block maxima of the next step's CFL speed.  With BULK (constant bulk momentum)
+// the force is left to bulk_force_apply_kernel, and each block writes the sums of
+// (rho U)~ V, (rho^n + rho~) V and V over its cells to mpart instead.
+template <typename TF, bool BULK>
 __global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __restrict__ rr, const TF* __restrict__ fl,
                                                      const double* __restrict__ qn, double* __restrict__ qout,
-                                                     Ctrl* ctrl, double* __restrict__ part, int step) {
+                                                     Ctrl* ctrl, double* __restrict__ part,
+                                                     double* __restrict__ mpart, int step) {
   if (ctrl->flag) return;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const double dt = ctrl->dt;
-  double speed = 0.0;
+  double speed = 0.0, sm = 0.0, ss = 0.0, sv = 0.0;
   if (idx < g.N) {
     int c[3];
     cell_coords<0>(g, idx, c);
@@ -205,15 +234,79 @@ __global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __rest
       divergence(g, fl, idx, c, k, nullptr, &dL);
       Qn[k] = rr[(long long)k * g.N + idx] + (dt * dt / 3.0) * dL;
     }
-    if (g.fx != 0.0) {
+    if (!BULK && g.fx != 0.0) {
       const double mx_old = qn[g.N + idx];
       Qn[1] = Qn[1] + 0.5 * dt * (Qn[0] + qn[idx]) * g.fx;
       Qn[4] = Qn[4] + 0.5 * dt * (Qn[1] + mx_old) * g.fx;
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) qout[(long long)k * g.N + idx] = Qn[k];
+    if constexpr (BULK) {
+      const double V = cell_volume(g, c[1]);
+      sm = Qn[1] * V;
+      ss = (qn[idx] + Qn[0]) * V;
+      sv = V;
+    } else {
+      bool ok;
+      speed = cell_speed(g, Qn, c[1], ok);
+      if (!ok) {
+        ctrl->fail_step = step;
+        ctrl->flag = 1;
+      }
+    }
+  }
+  if constexpr (BULK) block_sums3(sm, ss, sv, mpart + 3 * (long long)blockIdx.x);
+  else block_max_speed(speed, part);
+}
+
+// The step's force for constant bulk momentum (Sec. 3.3) from the stage-2 block
+// sums, combined in a fixed order: f_x = (m_b vol - M~) / (dt/2 S), with M~ the
+// box integral of the unforced (rho U)~, S that of rho^n + rho~ and vol the box
+// volume.  One block.
+__global__ void __launch_bounds__(256) bulk_force_kernel(const double* __restrict__ mpart, int nblocks, Ctrl* ctrl,
+                                                         double m_b, double* __restrict__ fx_out) {
+  __shared__ double tot[3];
+  __shared__ int stop;
+  if (threadIdx.x == 0) stop = ctrl->flag;
+  __syncthreads();
+  if (stop) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    a += mpart[3 * (long long)i];
+    b += mpart[3 * (long long)i + 1];
+    c += mpart[3 * (long long)i + 2];
+  }
+  block_sums3(a, b, c, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) *fx_out = (m_b * tot[2] - tot[0]) / (0.5 * ctrl->dt * tot[1]);
+}
+
+// Applies the force by the trapezoidal rule of stage2_kernel to the unforced
+// state in qout; physicality and the next step's CFL block maxima as there.
+__global__ void __launch_bounds__(256) bulk_force_apply_kernel(Geo g, const double* __restrict__ qn,
+                                                               double* __restrict__ qout, Ctrl* ctrl,
+                                                               const double* __restrict__ fxp,
+                                                               double* __restrict__ part, int step) {
+  __shared__ int stop;
+  if (threadIdx.x == 0) stop = ctrl->flag;
+  __syncthreads();
+  if (stop) return;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double speed = 0.0;
+  if (idx < g.N) {
+    const double dt = ctrl->dt, fx = *fxp;
+    double Q[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k] = qout[(long long)k * g.N + idx];
+    const double mx_old = qn[g.N + idx];
+    Q[1] = Q[1] + 0.5 * dt * (Q[0] + qn[idx]) * fx;
+    Q[4] = Q[4] + 0.5 * dt * (Q[1] + mx_old) * fx;
+    qout[g.N + idx] = Q[1];
+    qout[4 * g.N + idx] = Q[4];
+    int c[3];
+    cell_coords<0>(g, idx, c);
     bool ok;
-    speed = cell_speed(g, Qn, c[1], ok);
+    speed = cell_speed(g, Q, c[1], ok);
     if (!ok) {
       ctrl->fail_step = step;
       ctrl->flag = 1;
@@ -315,13 +408,25 @@ template void launch_stage1<float>(const Geo&, const double*, const float*, doub
 
 template <typename TF>
 void launch_stage2(const Geo& g, const double* rr, const TF* fl, const double* qn, double* qout, Ctrl* ctrl,
-                   double* part, int step, hipStream_t st) {
-  stage2_kernel<TF><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qn, qout, ctrl, part, step);
+                   double* part, double* mpart, int step, hipStream_t st) {
+  if (mpart)
+    stage2_kernel<TF, true><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qn, qout, ctrl, part, mpart, step);
+  else
+    stage2_kernel<TF, false><<<blocks_for(g.N), 256, 0, st>>>(g, rr, fl, qn, qout, ctrl, part, nullptr, step);
 }
 template void launch_stage2<double>(const Geo&, const double*, const double*, const double*, double*, Ctrl*, double*,
-                                    int, hipStream_t);
+                                    double*, int, hipStream_t);
 template void launch_stage2<float>(const Geo&, const double*, const float*, const double*, double*, Ctrl*, double*,
-                                   int, hipStream_t);
+                                   double*, int, hipStream_t);
+
+// mflux holds 3 * blocks_for(N) block sums, then the force
+void launch_bulk_force(const Geo& g, const double* qn, double* qout, Ctrl* ctrl, double* mflux, double m_b,
+                       double* part, int step, hipStream_t st) {
+  const unsigned nb = blocks_for(g.N);
+  double* fx = mflux + 3 * size_t(nb);
+  bulk_force_kernel<<<1, 256, 0, st>>>(mflux, int(nb), ctrl, m_b, fx);
+  bulk_force_apply_kernel<<<nb, 256, 0, st>>>(g, qn, qout, ctrl, fx, part, step);
+}
 
 void launch_check_state(const Geo& g, const double* q, Ctrl* ctrl, double* part, int step, hipStream_t st) {
   check_state_kernel<<<blocks_for(g.N), 256, 0, st>>>(g, q, ctrl, part, step);

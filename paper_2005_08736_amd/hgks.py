@@ -55,7 +55,7 @@ class HgksParams(ctypes.Structure):
         ("mode", ctypes.c_int32), ("cfl", ctypes.c_double),
         ("c_art", ctypes.c_double), ("weno_eps", ctypes.c_double), ("weno_p", ctypes.c_int32),
         ("T_wall", ctypes.c_double), ("body_force_x", ctypes.c_double),
-        ("precision", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("bulk_momentum", ctypes.c_double),
     ]
 
 

@@ -199,3 +199,46 @@ def test_channel128_full_size_sampled_step():
         got = q1[:, c[2], c[1], c[0]]
         ref = qw[:, 6, c[1], 6]
         assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(np.abs(ref), 1.0)), (c, got - ref)
+
+
+@pytest.mark.parametrize("precision", [hgks.PREC_F64, hgks.PREC_F32FLUX])
+def test_channel_constant_bulk_momentum(precision):
+    """Constant bulk momentum (Sec. 3.3) on the stretched 32x32x16 channel: the
+    box integral of rho U equals its target after every step (both forms, to 1e-13);
+    the FP64 path matches the oracle every step (1e-12, as the constant-force
+    steps)."""
+    p = cases.channel_params(32, 32, 16, body_force_x=0.0, bulk_momentum=1.0)
+    p["precision"] = precision
+    q = cases.channel_state(p)
+    target = 1.0 * p["lx"] * 2.0 * p["lz"]
+    announce(f"channel constant bulk momentum, precision {precision}")
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    qr = q.copy()
+    for i in range(4):
+        dts = s.step(1, return_dt=True)
+        m = s.diagnostics()["mom_x"]
+        assert abs(m - target) <= 1e-13 * target, (i, m, target)
+        if precision == hgks.PREC_F64:
+            qr, dtr = oracle.step(p, qr, 1)
+            assert abs(dts[0] - dtr[0]) <= 1e-14 * dtr[0], (i, dts[0], dtr[0])
+            errs = rel_l2_fields(qd.cpu().numpy(), qr)
+            assert max(errs) <= 1e-12, (i, errs)
+    announce(f"  total x-momentum {m:.15e}, target {target:.15e}")
+    s.close()
+
+
+def test_constant_bulk_momentum_argument_checks():
+    p = cases.channel_params(16, 12, 8, bulk_momentum=1.0)  # with the constant force of the defaults
+    with pytest.raises(hgks.HgksError) as e:
+        hgks.Solver(p, to_dev(cases.channel_state(p)))
+    assert e.value.status == hgks.HGKS_E_INVALID_ARG
+    # the step adjoint does not cover the forced step
+    pp = cases.params(nx=8, ny=8, nz=8, lx=1.0, ly=1.0, lz=1.0, bulk_momentum=0.3)
+    q = cases.uniform_state(8, 8, 8)
+    s = hgks.Solver(pp, to_dev(q))
+    lam = torch.ones((5, 8, 8, 8), dtype=torch.float64, device=dev())
+    with pytest.raises(hgks.HgksError) as e:
+        s.step_vjp(to_dev(q), 1e-3, lam)
+    assert e.value.status == hgks.HGKS_E_UNSUPPORTED
+    s.close()

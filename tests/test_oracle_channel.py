@@ -49,3 +49,31 @@ def test_channel_poiseuille_balance_converges_in_the_interior():
         errs.append(float(np.abs(e[k:-k]).max()))
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.5, errs
     assert errs[2] < 0.01 * 3.0 * 1e-2, errs  # below 1% of the force at ny = 128
+
+
+def test_constant_bulk_momentum_holds_its_target_every_step():
+    """With bulk_momentum = m_b the force of each step (Sec. 3.3) makes the box
+    integral of rho U equal m_b |Omega| after the step, whatever the unforced
+    update did; a dropped factor 1/2, a wrong sign or the wrong density in the
+    force formula leaves a residual of the size of the correction itself.  The
+    initial field's total differs from the target by 0.2%."""
+    p = cases.channel_params(12, 10, 8, body_force_x=0.0, bulk_momentum=1.0)
+    q = cases.channel_state(p)
+    vol = p["lx"] * 2.0 * p["lz"]
+    target = 1.0 * vol
+    m0 = oracle.diagnostics(p, q)["mom_x"]
+    assert abs(m0 - target) > 1e-3 * target
+    for i in range(3):
+        q, _ = oracle.step(p, q, 1)
+        m = oracle.diagnostics(p, q)["mom_x"]
+        assert abs(m - target) <= 1e-13 * target, (i, m, target)
+
+
+def test_constant_bulk_momentum_and_a_constant_force_exclude_each_other():
+    p = cases.channel_params(8, 8, 8, bulk_momentum=1.0)  # body_force_x = 2.93e-3 by default
+    q = cases.channel_state(p)
+    try:
+        oracle.step(p, q, 1)
+    except RuntimeError:
+        return
+    raise AssertionError("the oracle accepted a constant force together with constant bulk momentum")
