@@ -83,3 +83,27 @@ def test_plane_profiles_null_output_is_rejected():
         assert hgks.load().hgks_plane_profiles(s._h, None) == hgks.HGKS_E_INVALID_ARG
     finally:
         s.close()
+
+
+def test_total_stress_of_laminar_poiseuille_from_device_profiles():
+    """The device profiles of a laminar Poiseuille state (U = 1.5 (1 - y^2) at the
+    row centres of the stretched channel mesh, rho = 1, T = T_w) give a zero
+    total-stress residual in wall units (paper_2005_08736_amd.stats)."""
+    from paper_2005_08736_amd import stats
+    nx, ny, nz = 16, 64, 8
+    p = cases.channel_params(nx, ny, nz)
+    _, yc = cases.channel_y(ny, p["stretch_b"])
+    U = np.broadcast_to((1.5 * (1 - yc * yc))[None, :, None], (nz, ny, nx))
+    q = np.zeros((5, nz, ny, nx))
+    q[0] = 1.0
+    q[1] = U
+    q[4] = p["T_wall"] / (p["gamma"] - 1) + 0.5 * U * U
+    s = hgks.Solver(p, torch.from_numpy(q).to(dev()))
+    try:
+        prof = s.plane_profiles()
+    finally:
+        s.close()
+    r = stats.total_stress(prof, p, yc)
+    announce(f"laminar Poiseuille: u_tau {r['u_tau']:.6e}, Re_tau {r['Re_tau']:.3f}, "
+             f"max |residual| {np.abs(r['residual']).max():.1e}")
+    assert np.abs(r["residual"]).max() <= 1e-10
