@@ -242,3 +242,27 @@ def test_constant_bulk_momentum_argument_checks():
         s.step_vjp(to_dev(q), 1e-3, lam)
     assert e.value.status == hgks.HGKS_E_UNSUPPORTED
     s.close()
+
+
+def test_constant_bulk_momentum_periodic_mode_z():
+    """The same forcing on a periodic mode-Z box (isotropic 16^3, Ma_t 0.5, seeded
+    field, target mean rho U 0.1): the box momentum at its target and the state
+    matching the oracle every step."""
+    n = 16
+    p = cases.isotropic_params(n, 0.5)
+    p["bulk_momentum"] = 0.1
+    q = cases.isotropic_state(n, 0, 0.5)
+    target = 0.1 * p["lx"] * p["ly"] * p["lz"]
+    announce("constant bulk momentum, periodic mode Z 16^3")
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    qr = q.copy()
+    for i in range(2):
+        dts = s.step(1, return_dt=True)
+        qr, dtr = oracle.step(p, qr, 1)
+        m = s.diagnostics()["mom_x"]
+        assert abs(m - target) <= 1e-13 * target, (i, m, target)
+        assert abs(dts[0] - dtr[0]) <= 1e-14 * dtr[0], (i, dts[0], dtr[0])
+        errs = rel_l2_fields(qd.cpu().numpy(), qr)
+        assert max(errs) <= 1e-12, (i, errs)
+    s.close()

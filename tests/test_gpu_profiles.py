@@ -107,3 +107,13 @@ def test_total_stress_of_laminar_poiseuille_from_device_profiles():
     announce(f"laminar Poiseuille: u_tau {r['u_tau']:.6e}, Re_tau {r['Re_tau']:.3f}, "
              f"max |residual| {np.abs(r['residual']).max():.1e}")
     assert np.abs(r["residual"]).max() <= 1e-10
+
+
+def test_plane_profiles_fp32_form_workspace():
+    """The FP32-flux form has half the face-flux workspace that the profiles use
+    as scratch; the results are the same FP64 averages."""
+    nx, ny, nz = 20, 14, 11
+    L = (1.0, 2.0, 0.7)
+    p = cases.params(nx=nx, ny=ny, nz=nz, lx=L[0], ly=L[1], lz=L[2])
+    p["precision"] = hgks.PREC_F32FLUX
+    compare(p, random_state(nx, ny, nz, L, seed=5), "periodic random, FP32-flux form")
