@@ -181,6 +181,18 @@ int hgks_diagnostics(hgks_handle* h, double* out);
 #define HGKS_PDF_MAX_BINS 4096
 int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int64_t* counts, double* theta_rms);
 
+/* The normalized dilatation r = theta / theta_rms (defined as for
+ * hgks_dilatation_pdf) on one plane of cells, the data of the slice contours of
+ * Sec. 3.4: the cells whose index along axis (0 x, 1 y, 2 z) is index.  out (host)
+ * receives the plane's cells with the two remaining axes in the state's order,
+ * the slower one first: [nz][ny] for axis 0, [nz][nx] for axis 1, [ny][nx] for
+ * axis 2.  theta_rms (host) receives theta_rms over the whole box.  Errors:
+ * HGKS_E_INVALID_ARG for NULL pointers, axis outside 0..2 or index outside the
+ * axis; HGKS_E_UNSUPPORTED on a stretched mesh.  Uses the diagnostics' block
+ * partials and the face-flux arrays of the workspace as scratch; enqueued on the
+ * handle's stream, which it synchronizes. */
+int hgks_dilatation_slice(hgks_handle* h, int32_t axis, int32_t index, double* out, double* theta_rms);
+
 /* Plane-averaged profiles of the bound state per y row, the statistics of the
  * channel in Sec. 3.3 (mean velocity, velocity fluctuations, Reynolds stress, and
  * the total-stress balance built from them): Reynolds averages <.> over the

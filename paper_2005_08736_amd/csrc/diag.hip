@@ -320,6 +320,35 @@ void launch_dilatation_pdf(const Geo& g, const double* q, double* part, int nbin
   dil_hist_kernel<<<kDiagBlocks, kDilThreads, 0, st>>>(g, q, part, nbins, lo, hi, double(nbins) / (hi - lo));
 }
 
+// theta / theta_rms on the plane `index` of `axis` (the slices whose contours
+// Sec. 3.4 shows), rms from the partial buffer; out holds the plane's cells with
+// the two remaining axes in state order (slower first, faster fastest)
+__global__ void __launch_bounds__(256) dil_slice_kernel(Geo g, const double* __restrict__ q,
+                                                        const double* __restrict__ part, int axis, int index,
+                                                        double* __restrict__ out) {
+  const int fa = axis == 0 ? 1 : 0;  // faster remaining axis
+  const int sa = axis == 2 ? 1 : 2;  // slower remaining axis
+  const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (m >= (long long)g.n[fa] * g.n[sa]) return;
+  int c[3];
+  c[axis] = index;
+  c[fa] = int(m % g.n[fa]);
+  c[sa] = int(m / g.n[fa]);
+  const long long idx = (long long)c[0] + (long long)c[1] * g.stride[1] + (long long)c[2] * g.stride[2];
+  const double rms = part[kDiagBlocks];
+  const double th = dilatation_at(g, q, idx, c);
+  out[m] = rms > 0.0 ? th / rms : 0.0;
+}
+
+void launch_dilatation_slice(const Geo& g, const double* q, double* part, int axis, int index, double* out,
+                             hipStream_t st) {
+  dil_sum_kernel<<<kDiagBlocks, kDilThreads, 0, st>>>(g, q, part);
+  dil_rms_kernel<<<1, 256, 0, st>>>(g, part, 0);
+  const int fa = axis == 0 ? 1 : 0, sa = axis == 2 ? 1 : 2;
+  const long long cells = (long long)g.n[fa] * g.n[sa];
+  dil_slice_kernel<<<unsigned((cells + 255) / 256), 256, 0, st>>>(g, q, part, axis, index, out);
+}
+
 // ---- plane-averaged profiles per y row (Sec. 3.3: mean velocity, velocity
 // fluctuations and Reynolds stress of the channel).  One block per row; Reynolds
 // averages over the row's nx * nz cells, the second moments about the row means

@@ -493,6 +493,23 @@ int hgks_dilatation_pdf(hgks_handle* h, int32_t nbins, double lo, double hi, int
   return hip_status(hipStreamSynchronize(h->stream));
 }
 
+int hgks_dilatation_slice(hgks_handle* h, int32_t axis, int32_t index, double* out, double* theta_rms) {
+  if (!h || !out || !theta_rms || axis < 0 || axis > 2) return HGKS_E_INVALID_ARG;
+  if (index < 0 || index >= h->geo.n[axis]) return HGKS_E_INVALID_ARG;
+  if (h->geo.stretch_y) return HGKS_E_UNSUPPORTED;
+  const int fa = axis == 0 ? 1 : 0, sa = axis == 2 ? 1 : 2;
+  const size_t cells = size_t(h->geo.n[fa]) * size_t(h->geo.n[sa]);  // < N / 6, inside the face-flux arrays
+  double* scratch = reinterpret_cast<double*>(h->fl);
+  launch_dilatation_slice(h->geo, h->q, h->diag_part, axis, index, scratch, h->stream);
+  if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(theta_rms, h->diag_part + dilatation_pdf_rms_offset(), sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  if (hipMemcpyAsync(out, scratch, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    return HGKS_E_DEVICE;
+  return hip_status(hipStreamSynchronize(h->stream));
+}
+
 static_assert(HGKS_NPROFILE == kNProfile, "one profile width");
 
 int hgks_plane_profiles(hgks_handle* h, double* out) {

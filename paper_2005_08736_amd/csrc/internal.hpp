@@ -47,6 +47,9 @@ void launch_dilatation_pdf(const Geo& g, const double* q, double* part, int nbin
                            hipStream_t st);
 size_t dilatation_pdf_rms_offset();
 size_t dilatation_pdf_counts_offset();
+// theta / theta_rms on one plane of cells, written to out (device)
+void launch_dilatation_slice(const Geo& g, const double* q, double* part, int axis, int index, double* out,
+                             hipStream_t st);
 // plane-averaged profiles per y row: kNProfile doubles per row
 constexpr int kNProfile = 11;
 void launch_plane_profiles(const Geo& g, const double* q, double* out, hipStream_t st);

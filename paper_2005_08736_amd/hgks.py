@@ -38,7 +38,7 @@ EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
     "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp", "hgks_dilatation_pdf",
-    "hgks_plane_profiles",
+    "hgks_plane_profiles", "hgks_dilatation_slice",
 ]
 PDF_MAX_BINS = 4096
 PROFILE_NAMES = ["rho", "U", "V", "W", "p", "T", "uu", "vv", "ww", "uv", "rhoU"]
@@ -105,6 +105,8 @@ def load():
     L.hgks_dilatation_pdf.argtypes = [vp, ctypes.c_int32, dbl, dbl, ctypes.POINTER(ctypes.c_int64), D]
     L.hgks_plane_profiles.restype = ctypes.c_int
     L.hgks_plane_profiles.argtypes = [vp, D]
+    L.hgks_dilatation_slice.restype = ctypes.c_int
+    L.hgks_dilatation_slice.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, D, D]
     L.hgks_strerror.restype = ctypes.c_char_p
     L.hgks_strerror.argtypes = [ctypes.c_int]
     _lib = L
@@ -211,6 +213,19 @@ class Solver:
                                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(rms)),
                "hgks_dilatation_pdf")
         return counts, rms.value
+
+    def dilatation_slice(self, axis: int, index: int):
+        """theta / theta_rms on the plane `index` of `axis` (hgks_dilatation_slice):
+        returns (plane, theta_rms), plane shaped by the two remaining axes in state
+        order ([nz, ny], [nz, nx] or [ny, nx])."""
+        n = [self.params["nx"], self.params["ny"], self.params["nz"]]
+        fa, sa = (1 if axis == 0 else 0), (1 if axis == 2 else 2)
+        out = np.zeros((n[sa], n[fa]))
+        rms = ctypes.c_double(0.0)
+        _check(load().hgks_dilatation_slice(self._h, int(axis), int(index),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rms)),
+               "hgks_dilatation_slice")
+        return out, rms.value
 
     def plane_profiles(self) -> np.ndarray:
         """Per-y-row plane averages (hgks_plane_profiles): array [ny, 11], columns

@@ -165,3 +165,57 @@ def test_dilatation_pdf_errors_through_the_c_abi():
         assert e.value.status == hgks.HGKS_E_UNSUPPORTED
     finally:
         sc.close()
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_dilatation_slices_match_oracle(axis):
+    """theta / theta_rms on the first, a middle and the last plane of each axis
+    (the slices of the contour figure of Sec. 3.4), element by element against
+    the oracle's per-cell dilatation divided by its rms, on a ragged periodic
+    box and a walled uniform-mesh box (whose y-planes 0 and ny-1 touch the
+    walls)."""
+    boxes = []
+    nx, ny, nz = 20, 14, 11
+    L = (1.0 * nx / 16, 1.5 * ny / 16, 0.8 * nz / 16)
+    boxes.append((cases.params(nx=nx, ny=ny, nz=nz, lx=L[0], ly=L[1], lz=L[2]), random_state(nx, ny, nz, L, seed=31)))
+    pw = cases.channel_params(24, 18, 16, stretch_b=0.0, ly=2.0)
+    boxes.append((pw, random_state(24, 18, 16, (pw["lx"], pw["ly"], pw["lz"]), seed=32)))
+    for p, q in boxes:
+        n = [p["nx"], p["ny"], p["nz"]]
+        th = oracle.dilatation(p, q)  # [nz][ny][nx]
+        rms = float(np.sqrt(np.mean(th * th)))
+        s = hgks.Solver(p, torch.from_numpy(np.ascontiguousarray(q)).to(dev()))
+        try:
+            for index in (0, n[axis] // 2, n[axis] - 1):
+                got, rms_gpu = s.dilatation_slice(axis, index)
+                ref = (th[:, :, index] if axis == 0 else th[:, index, :] if axis == 1 else th[index]) / rms
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                announce(f"slice axis {axis} index {index} of {n}: max error {err:.1e}")
+                assert abs(rms_gpu - rms) <= 1e-12 * rms
+                assert err <= 1e-12
+        finally:
+            s.close()
+
+
+def test_dilatation_slice_argument_checks():
+    p = cases.params(nx=8, ny=7, nz=6, lx=1.0, ly=1.0, lz=1.0)
+    s = hgks.Solver(p, torch.from_numpy(cases.uniform_state(8, 7, 6)).to(dev()))
+    L = hgks.load()
+    out = np.zeros(8 * 8)
+    op = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rms = ctypes.c_double()
+    try:
+        for axis, index in [(-1, 0), (3, 0), (0, 8), (1, 7), (2, 6), (2, -1)]:
+            assert L.hgks_dilatation_slice(s._h, axis, index, op, ctypes.byref(rms)) == hgks.HGKS_E_INVALID_ARG
+        plane, r = s.dilatation_slice(2, 5)
+        assert plane.shape == (7, 8) and r == 0.0 and np.all(plane == 0.0)
+    finally:
+        s.close()
+    pc = cases.channel_params(16, 16, 16)
+    sc = hgks.Solver(pc, torch.from_numpy(cases.channel_state(pc)).to(dev()))
+    try:
+        with pytest.raises(hgks.HgksError) as e:
+            sc.dilatation_slice(1, 0)
+        assert e.value.status == hgks.HGKS_E_UNSUPPORTED
+    finally:
+        sc.close()
