@@ -508,6 +508,14 @@ static const Weights& weights() {
   return w;
 }
 
+// x^p for the integer exponent p >= 1 of the WENO-Z weights, by repeated products.
+template <class R>
+static R int_power(const R& x, int p) {
+  R y = x;
+  for (int i = 1; i < p; ++i) y = y * x;
+  return y;
+}
+
 // Fifth-order WENO (Jiang-Shu sub-stencils, WENO-Z weights): value and slope at
 // the right edge of cell 2 of the five cells v[0..4].  linear = true uses the
 // optimal weights d = (1/10, 6/10, 3/10).
@@ -532,14 +540,54 @@ static void weno5_right_edge(const R* v, bool linear, double eps, int p, R& val,
     R b2 = R(13.0 / 12.0) * (v[2] - R(2.0) * v[3] + v[4]) * (v[2] - R(2.0) * v[3] + v[4]) +
            R(0.25) * (R(3.0) * v[2] - R(4.0) * v[3] + v[4]) * (R(3.0) * v[2] - R(4.0) * v[3] + v[4]);
     R tau5 = fabs(b0 - b2);
-    R a0 = R(0.1) * (R(1.0) + pow(tau5 / (b0 + R(eps)), double(p)));
-    R a1 = R(0.6) * (R(1.0) + pow(tau5 / (b1 + R(eps)), double(p)));
-    R a2 = R(0.3) * (R(1.0) + pow(tau5 / (b2 + R(eps)), double(p)));
+    R a0 = R(0.1) * (R(1.0) + int_power(tau5 / (b0 + R(eps)), p));
+    R a1 = R(0.6) * (R(1.0) + int_power(tau5 / (b1 + R(eps)), p));
+    R a2 = R(0.3) * (R(1.0) + int_power(tau5 / (b2 + R(eps)), p));
     R sum = a0 + a1 + a2;
     w0 = a0 / sum; w1 = a1 / sum; w2 = a2 / sum;
   }
   val = w0 * q0 + w1 * q1 + w2 * q2;
   slope = w0 * d1_0 + w1 * d1_1 + w2 * d1_2;
+}
+
+// Tangential reconstruction along one line of five face averages v[0..4] centred
+// on the face v[2], to the two Gauss points s = -+1/(2 sqrt 3) of that face
+// (index 0 at -, 1 at +): value and derivative per unit width (Remark 1 of Sec. 2.1).
+//   smooth (mode S): the quartic matching the five averages;
+//   WENO-Z (mode Z): the edge values a (left) and b (right) of the middle face by
+//     WENO-Z from the five averages, then the quadratic with those edge values and
+//     the average m, m + (b - a) x + 3 (a + b - 2m)(x^2 - 1/12) on [-1/2, 1/2]:
+//     value m + s (b - a),  derivative (b - a) + 6 s (a + b - 2m), where
+//     6 s = -+sqrt(3).
+template <class R>
+struct LineAtGauss {
+  R val[2], der[2];
+};
+
+template <class R>
+static LineAtGauss<R> tangential_line(const R* v, bool weno, double eps, int p) {
+  LineAtGauss<R> out;
+  if (!weno) {
+    const Weights& W = weights();
+    for (int g = 0; g < 2; ++g) {
+      R x = R(0.0), d = R(0.0);
+      for (int s = 0; s < 5; ++s) { x = x + R(W.tan_val[g][s]) * v[s]; d = d + R(W.tan_der[g][s]) * v[s]; }
+      out.val[g] = x;
+      out.der[g] = d;
+    }
+    return out;
+  }
+  R a, b, unused, mirror[5];
+  for (int s = 0; s < 5; ++s) mirror[s] = v[4 - s];
+  weno5_right_edge(v, false, eps, p, b, unused);
+  weno5_right_edge(mirror, false, eps, p, a, unused);
+  const R m = v[2];
+  for (int g = 0; g < 2; ++g) {
+    const R sgn = R(g == 0 ? -1.0 : 1.0);
+    out.val[g] = m + sgn * (b - a) * R(1.0 / (2.0 * std::sqrt(3.0)));
+    out.der[g] = (b - a) + sgn * R(std::sqrt(3.0)) * (a + b - R(2.0) * m);
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -770,12 +818,40 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
         }
       }
 
-  // ---- tangential reconstruction to the 2x2 Gauss points and the flux there
+  // ---- tangential reconstruction to the 2x2 Gauss points and the flux there.
+  // Every face field is reconstructed along t1 on the five rows t2 = t-2..t+2
+  // (values and t1-derivatives at the two t1 Gauss points), then along t2 from
+  // those row values (value and t2-derivative) and row derivatives (t1-derivative).
   const double gs = 1.0 / (2.0 * std::sqrt(3.0));
 #pragma omp parallel for collapse(2) schedule(static)
   for (int t = 0; t < N2; ++t)
     for (int a = 0; a < N1; ++a)
       for (int nn = -1; nn < Nn; ++nn) {
+        // gv/g1/g2[m][l][field]: value, d/dt1, d/dt2 at the Gauss point (m, l)
+        R gv[2][2][30], g1[2][2][30], g2[2][2][30];
+        for (int fld = 0; fld < nfield; ++fld) {
+          LineAtGauss<R> rows[5];
+          for (int r = 0; r < 5; ++r) {
+            R line[5];
+            for (int s = 0; s < 5; ++s) {
+              int ijk[3];
+              f.cell(nn, a - 2 + s, t - 2 + r, ijk);
+              line[s] = ff.at(fld, ijk);
+            }
+            rows[r] = tangential_line(line, full, P.weno_eps, P.weno_p);
+          }
+          for (int m = 0; m < 2; ++m) {
+            R rowv[5], rowd[5];
+            for (int r = 0; r < 5; ++r) { rowv[r] = rows[r].val[m]; rowd[r] = rows[r].der[m]; }
+            LineAtGauss<R> along_v = tangential_line(rowv, full, P.weno_eps, P.weno_p);
+            LineAtGauss<R> along_d = tangential_line(rowd, full, P.weno_eps, P.weno_p);
+            for (int l = 0; l < 2; ++l) {
+              gv[m][l][fld] = along_v.val[l];
+              g2[m][l][fld] = along_v.der[l];
+              g1[m][l][fld] = along_d.val[l];
+            }
+          }
+        }
         R Fsum[5], dFsum[5];
         for (int c = 0; c < 5; ++c) Fsum[c] = dFsum[c] = R(0.0);
         for (int m = 0; m < 2; ++m)      // t1 Gauss point
@@ -786,57 +862,9 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
             // value, d/dt1, d/dt2 of every face field at (s1, s2)
             R val[30], d1[30], d2[30];
             for (int fld = 0; fld < nfield; ++fld) {
-              R rowv[5], rowd[5];
-              for (int r = 0; r < 5; ++r) {  // t2 rows t-2..t+2; reconstruct along t1 first
-                R line[5];
-                for (int s = 0; s < 5; ++s) {
-                  int ijk[3];
-                  f.cell(nn, a - 2 + s, t - 2 + r, ijk);
-                  line[s] = ff.at(fld, ijk);
-                }
-                if (!full) {
-                  R v = R(0.0), dd = R(0.0);
-                  for (int s = 0; s < 5; ++s) { v = v + R(W.tan_val[m][s]) * line[s]; dd = dd + R(W.tan_der[m][s]) * line[s]; }
-                  rowv[r] = v; rowd[r] = dd;
-                } else {
-                  R ea, eb, sa, sb;  // edge values of the middle cell from WENO-Z
-                  R mirror[5];
-                  for (int s = 0; s < 5; ++s) mirror[s] = line[4 - s];
-                  weno5_right_edge(line, false, P.weno_eps, P.weno_p, eb, sb);
-                  weno5_right_edge(mirror, false, P.weno_eps, P.weno_p, ea, sa);
-                  (void)sa; (void)sb;
-                  R mm = line[2];
-                  R sgn = R(m == 0 ? -1.0 : 1.0);
-                  rowv[r] = mm + sgn * (eb - ea) * R(gs);
-                  rowd[r] = (eb - ea) + sgn * R(std::sqrt(3.0)) * (ea + eb - R(2.0) * mm);
-                }
-              }
-              // along t2
-              if (!full) {
-                R v = R(0.0), dv2 = R(0.0), dv1 = R(0.0);
-                for (int r = 0; r < 5; ++r) {
-                  v = v + R(W.tan_val[l][r]) * rowv[r];
-                  dv2 = dv2 + R(W.tan_der[l][r]) * rowv[r];
-                  dv1 = dv1 + R(W.tan_val[l][r]) * rowd[r];
-                }
-                val[fld] = v; d1[fld] = dv1 * R(inv1); d2[fld] = dv2 * R(inv2);
-              } else {
-                auto quad = [&](const R* line, R& v, R& dv) {
-                  R ea, eb, sa, sb, mirror[5];
-                  for (int s = 0; s < 5; ++s) mirror[s] = line[4 - s];
-                  weno5_right_edge(line, false, P.weno_eps, P.weno_p, eb, sb);
-                  weno5_right_edge(mirror, false, P.weno_eps, P.weno_p, ea, sa);
-                  (void)sa; (void)sb;
-                  R mm = line[2];
-                  R sgn = R(l == 0 ? -1.0 : 1.0);
-                  v = mm + sgn * (eb - ea) * R(gs);
-                  dv = (eb - ea) + sgn * R(std::sqrt(3.0)) * (ea + eb - R(2.0) * mm);
-                };
-                R v, dv2, dv1, unused;
-                quad(rowv, v, dv2);
-                quad(rowd, dv1, unused);
-                val[fld] = v; d1[fld] = dv1 * R(inv1); d2[fld] = dv2 * R(inv2);
-              }
+              val[fld] = gv[m][l][fld];
+              d1[fld] = g1[m][l][fld] * R(inv1);
+              d2[fld] = g2[m][l][fld] * R(inv2);
             }
             R F[5], dF[5];
             R Q0[5], dQ0[3][5];
@@ -1431,6 +1459,18 @@ int hgks_ref_weights(double* out) {
   for (int m = 0; m < 2; ++m)
     for (int j = 0; j < 5; ++j) { out[m * 5 + j] = w.tan_val[m][j]; out[10 + m * 5 + j] = w.tan_der[m][j]; }
   for (int j = 0; j < 5; ++j) out[20 + j] = w.dn[j];
+  return 0;
+}
+
+// Tangential reconstruction of one line of five face averages (centred on v[2])
+// to the Gauss point gp (0: -1/(2 sqrt 3), 1: +1/(2 sqrt 3)) of the middle face:
+// value and derivative per unit width.  weno = 0: the quartic (mode S); 1: WENO-Z
+// edge values and the quadratic (mode Z).
+int hgks_ref_tangential_line(const double* v, int weno, double eps, int p, int gp, double* val, double* der) {
+  if (gp < 0 || gp > 1 || (weno && p < 1)) return -1;
+  ref::LineAtGauss<double> r = ref::tangential_line(v, weno != 0, eps, p);
+  *val = r.val[gp];
+  *der = r.der[gp];
   return 0;
 }
 
