@@ -39,7 +39,9 @@ _D = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        # HGKS_ORACLE_SANITIZED=1 selects the ASan + UBSan build (the sanitizer
+        # runtimes must then be preloaded into the process)
+        path = _build.build(force=False, sanitize=os.environ.get("HGKS_ORACLE_SANITIZED") == "1")
         L = ctypes.CDLL(path)
         P = ctypes.POINTER(RefParams)
         i32, dbl = ctypes.c_int, ctypes.c_double
@@ -49,6 +51,7 @@ def lib():
             "hgks_ref_step": (i32, [P, _D, i32, dbl, _D]),
             "hgks_ref_operator": (i32, [P, _D, dbl, _D, _D]),
             "hgks_ref_face_flux": (i32, [P, _D, i32, dbl, _D, _D]),
+            "hgks_ref_wall_flux": (i32, [P, _D, dbl, _D, _D]),
             "hgks_ref_diagnostics": (i32, [P, _D, _D]),
             "hgks_ref_ndiag": (i32, []),
             "hgks_ref_dilatation": (i32, [P, _D, _D]),
@@ -64,6 +67,7 @@ def lib():
             "hgks_ref_gp_flux_full_parts": (i32, [_D, _D, _D, _D, _D, _D, dbl, dbl, dbl, dbl, dbl, _D, _D]),
             "hgks_ref_weights": (i32, [_D]),
             "hgks_ref_weno5": (i32, [_D, i32, dbl, i32, _D, _D]),
+            "hgks_ref_tangential_line": (i32, [_D, i32, dbl, i32, i32, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -137,6 +141,19 @@ def face_flux(params: dict, q: np.ndarray, direction: int, dt: float = 0.0):
     dF = np.zeros_like(q)
     rc = lib().hgks_ref_face_flux(ctypes.byref(make_params(params)), _p(q), int(direction), float(dt), _p(F), _p(dF))
     _check(rc, "face_flux")
+    return F, dF
+
+
+def wall_flux(params: dict, q: np.ndarray, dt: float = 0.0):
+    """Fluxes of the wall faces of a channel: (F, dF), each [2][5][nz][nx] with
+    entry 0 the bottom wall (y = -1) and entry 1 the top wall (y = +1); global
+    frame, area-weighted like face_flux."""
+    q = _arr(q)
+    nz, nx = q.shape[1], q.shape[3]
+    F = np.zeros((2, 5, nz, nx))
+    dF = np.zeros((2, 5, nz, nx))
+    rc = lib().hgks_ref_wall_flux(ctypes.byref(make_params(params)), _p(q), float(dt), _p(F), _p(dF))
+    _check(rc, "wall_flux")
     return F, dF
 
 
@@ -320,5 +337,16 @@ def weno5(v, linear, eps=1e-6, p=2):
     return float(val[0]), float(slope[0])
 
 
+def tangential_line(v, weno, gp, eps=1e-6, p=2):
+    """One tangential line of five face averages to the Gauss point gp (0: -, 1: +)
+    of the middle face: (value, derivative per unit width).  weno False: the
+    quartic of mode S; True: WENO-Z edge values and the quadratic of mode Z."""
+    v = _arr(v, 5)
+    val = np.zeros(1)
+    der = np.zeros(1)
+    _check(lib().hgks_ref_tangential_line(_p(v), int(bool(weno)), float(eps), int(p), int(gp), _p(val), _p(der)),
+           "tangential_line")
+    return float(val[0]), float(der[0])
+
+
 __all__ = [n for n in dir() if not n.startswith("_")] + ["_build"]
-_ = os  # keep import (path helpers in build)

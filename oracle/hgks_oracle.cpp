@@ -1306,6 +1306,32 @@ int hgks_ref_face_flux(const ref_params* p, const double* q, int dir, double dt,
   return 0;
 }
 
+// Face fluxes of the two wall faces of every (x, z) column of a channel (bc_y = 1):
+// F and dF are [2][5][nz][nx], entry 0 the bottom wall y = -1 (face -1/2), entry 1
+// the top wall y = +1 (face ny-1/2); y-face fluxes in the global frame,
+// area-weighted, as hgks_ref_face_flux gives them.
+int hgks_ref_wall_flux(const ref_params* p, const double* q, double dt, double* F, double* dF) {
+  if (ref::validate(p) || p->bc_y != 1) return -1;
+  ref::Box<double> b(*p);
+  b.load(q);
+  ref::fill_ghosts(b);
+  const size_t np = size_t(5) * b.pn[0] * b.pn[1] * b.pn[2];
+  std::vector<double> Fn(np, 0.0), dFn(np, 0.0);
+  ref::face_fluxes(b, 1, dt, Fn, dFn);
+  const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
+  for (int w = 0; w < 2; ++w) {
+    const int j = w == 0 ? -1 : ny - 1;  // face j+1/2 is stored at the cell index j
+    for (int c = 0; c < 5; ++c)
+      for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+          size_t o = ((size_t(w) * 5 + c) * nz + k) * nx + i;
+          F[o] = Fn[b.idx(c, i, j, k)];
+          dF[o] = dFn[b.idx(c, i, j, k)];
+        }
+  }
+  return 0;
+}
+
 int hgks_ref_diagnostics(const ref_params* p, const double* q, double* out) {
   if (ref::validate(p)) return -1;
   ref::Box<double> b(*p);

@@ -14,8 +14,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# HGKS_LIB may point at another build of the same library (e.g. a tuning variant).
-LIB_PATH = os.environ.get("HGKS_LIB") or os.path.join(HERE, "libhgks.so")
+LIB_PATH = os.path.join(HERE, "libhgks.so")
 
 HGKS_OK = 0
 HGKS_E_INVALID_ARG = -1

@@ -64,3 +64,33 @@ def test_params_struct_matches_header_field_order():
     fields = [(n, "int32_t" if t.__name__ == "c_int" else "double") for n, t in hgks.HgksParams._fields_]
     assert [d[0] for d in decl] == [f[0] for f in fields]
     assert [d[1] for d in decl] == [f[1] for f in fields]
+
+
+def test_init_rejects_missing_small_or_misaligned_workspace():
+    """hgks_init checks the workspace before it touches the device: a NULL
+    workspace, one byte too few and a pointer off the 256-byte alignment all
+    return HGKS_E_WORKSPACE (the pointers are never dereferenced)."""
+    import ctypes
+
+    lib = hgks.load()
+    p = cases.tgv_params(8)
+    prm = hgks.make_params(p)
+    need = hgks.workspace_bytes(p)
+    fake_q = ctypes.c_void_p(1 << 20)
+    h = ctypes.c_void_p()
+    cases_ = [
+        (None, need),
+        (ctypes.c_void_p(1 << 21), need - 1),
+        (ctypes.c_void_p((1 << 21) + 128), need),
+        (ctypes.c_void_p((1 << 21) + 8), need + 256),
+    ]
+    for ws, nbytes in cases_:
+        rc = lib.hgks_init(ctypes.byref(prm), fake_q, ws, nbytes, None, ctypes.byref(h))
+        assert rc == hgks.HGKS_E_WORKSPACE, (ws, nbytes, rc)
+        assert not h.value
+    # invalid parameters are reported before the workspace
+    bad = dict(p, nx=5)
+    rc = lib.hgks_init(ctypes.byref(hgks.make_params(bad)), fake_q, None, 0, None, ctypes.byref(h))
+    assert rc == hgks.HGKS_E_INVALID_ARG
+    assert lib.hgks_init(ctypes.byref(prm), None, ctypes.c_void_p(1 << 21), need, None,
+                         ctypes.byref(h)) == hgks.HGKS_E_INVALID_ARG
