@@ -68,6 +68,7 @@ def lib():
             "hgks_ref_weights": (i32, [_D]),
             "hgks_ref_weno5": (i32, [_D, i32, dbl, i32, _D, _D]),
             "hgks_ref_tangential_line": (i32, [_D, i32, dbl, i32, i32, _D, _D]),
+            "hgks_ref_eigenvectors": (i32, [_D, dbl, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -347,6 +348,16 @@ def tangential_line(v, weno, gp, eps=1e-6, p=2):
     _check(lib().hgks_ref_tangential_line(_p(v), int(bool(weno)), float(eps), int(p), int(gp), _p(val), _p(der)),
            "tangential_line")
     return float(val[0]), float(der[0])
+
+
+def eigenvectors(Q, gamma):
+    """(R, L): right eigenvectors of the normal Euler-flux Jacobian at the
+    local-frame state Q (columns for u - c, u, u, u, u + c) and L = R^-1."""
+    Q = _arr(Q, 5)
+    R = np.zeros((5, 5))
+    L = np.zeros((5, 5))
+    lib().hgks_ref_eigenvectors(_p(Q), float(gamma), _p(R), _p(L))
+    return R, L
 
 
 __all__ = [n for n in dir() if not n.startswith("_")] + ["_build"]

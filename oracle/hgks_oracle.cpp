@@ -39,6 +39,12 @@
 //   - WENO-Z with exponent p and epsilon as parameters (default 2 and 1e-6) on
 //     conservative variables; the normal slopes of Q_l, Q_r use the nonlinear
 //     weights on the sub-stencil derivatives;
+//   - mode 2 (characteristic variables, the Remark on non-smooth flows): the
+//     normal reconstruction of a face projects its six cells with the left
+//     eigenvectors of the normal Euler-flux Jacobian at the mean of the face's
+//     two cells; the tangential reconstruction of a face projects the 5x5
+//     neighbouring face values of each field group with the eigenvectors at the
+//     face's own equilibrium state Q0, shared by its four Gauss points;
 //   - Prandtl-number fix: the energy flux gains (1/Pr - 1) q, q the normal heat
 //     flux, about the interface velocity, of the interface distribution;
 //   - local frame: x-faces (u,v,w), y-faces (v,w,u), z-faces (w,u,v);
@@ -87,7 +93,8 @@ extern "C" typedef struct {
   double stretch_b;    // 0: uniform y; >0: tanh map with this b_g (channel)
   double gamma, prandtl;
   double mu_ref, T_ref, mu_exp;  // mu(T) = mu_ref (T/T_ref)^mu_exp
-  int32_t mode;        // 0 smooth (linear weights + smooth flux), 1 WENO-Z + full flux
+  int32_t mode;        // 0 smooth (linear weights + smooth flux), 1 WENO-Z + full flux,
+                       // 2 WENO-Z in characteristic variables + full flux
   double cfl;
   double c_art, weno_eps;
   int32_t weno_p;
@@ -591,6 +598,62 @@ static LineAtGauss<R> tangential_line(const R* v, bool weno, double eps, int p) 
 }
 
 // ---------------------------------------------------------------------------
+// Characteristic variables (mode 2; the Remark of Sec. 2.1 on non-smooth flows):
+// omega = R^{-1} Q, with R the right eigenvectors of the Jacobian dF/dQ of the
+// Euler flux normal to the face, in the face's local frame (component 1 is the
+// normal momentum).  With velocity (u, v, w), sound speed c and total enthalpy
+// H = (rho E + p)/rho, the columns for the eigenvalues u - c, u, u, u, u + c are
+//   (1, u - c, v, w, H - u c), (1, u, v, w, |u|^2/2), (0, 0, 1, 0, v),
+//   (0, 0, 0, 1, w), (1, u + c, v, w, H + u c).
+// R^{-1} is formed by Gauss-Jordan elimination with partial pivoting.
+// ---------------------------------------------------------------------------
+template <class R>
+static void euler_eigenvectors(const R* Q, double gamma, R Rm[5][5]) {
+  Prim<R> s = primitive(Q, gamma);
+  const R c = sqrt(R(gamma) * s.p / s.rho);
+  const R H = (Q[4] + s.p) / s.rho;
+  const R u = s.U, v = s.V, w = s.W;
+  const R col[5][5] = {{R(1.0), u - c, v, w, H - u * c},
+                       {R(1.0), u, v, w, R(0.5) * (u * u + v * v + w * w)},
+                       {R(0.0), R(0.0), R(1.0), R(0.0), v},
+                       {R(0.0), R(0.0), R(0.0), R(1.0), w},
+                       {R(1.0), u + c, v, w, H + u * c}};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) Rm[i][j] = col[j][i];
+}
+
+template <class R>
+static void invert5(const R A[5][5], R Ainv[5][5]) {
+  R M[5][10];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 10; ++j) M[i][j] = j < 5 ? A[i][j] : R(j - 5 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 5; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 5; ++r)
+      if (std::fabs(value(M[r][c])) > std::fabs(value(M[piv][c]))) piv = r;
+    for (int j = 0; j < 10; ++j) std::swap(M[c][j], M[piv][j]);
+    const R inv = R(1.0) / M[c][c];
+    for (int j = 0; j < 10; ++j) M[c][j] = M[c][j] * inv;
+    for (int r = 0; r < 5; ++r) {
+      if (r == c) continue;
+      const R f = M[r][c];
+      for (int j = 0; j < 10; ++j) M[r][j] = M[r][j] - f * M[c][j];
+    }
+  }
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) Ainv[i][j] = M[i][5 + j];
+}
+
+template <class R>
+static void mat5_vec(const R A[5][5], const R* x, R* y) {
+  for (int i = 0; i < 5; ++i) {
+    R acc = R(0.0);
+    for (int j = 0; j < 5; ++j) acc = acc + A[i][j] * x[j];
+    y[i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Grid with explicit ghost layers.
 // ---------------------------------------------------------------------------
 constexpr int G = 3;  // ghost layers: the 6-cell normal stencil reaches 3 cells out
@@ -771,7 +834,8 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
   const ref_params& P = b.P;
   const Frame f(d);
   const int Nn = b.n[f.ax[0]], N1 = b.n[f.ax[1]], N2 = b.n[f.ax[2]];
-  const bool full = P.mode == 1;
+  const bool full = P.mode >= 1;  // WENO-Z and the full flux (modes 1 and 2)
+  const bool chr = P.mode == 2;   // WENO-Z in characteristic variables
   const int nfield = full ? 30 : 10;
   const Weights& W = weights();
   FaceField<R> ff;
@@ -788,14 +852,40 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
         double dn_scale = inv_hn;
         if (f.ax[0] == 1 && b.stretched) dn_scale = inv_metric(b, 1, double(nn + 1));
         R Ql[5], Qr[5], Dl[5], Dr[5], Dn[5], Q0[5];
+        // mode 2: WENO-Z on the characteristic variables of the state midway
+        // between the two cells of the face, then back to conservative variables
+        R Rm[5][5], Lm[5][5], vars[6][5];
+        if (chr) {
+          R mid[5];
+          for (int c = 0; c < 5; ++c) mid[c] = R(0.5) * (cells[2][c] + cells[3][c]);
+          euler_eigenvectors(mid, P.gamma, Rm);
+          invert5(Rm, Lm);
+          for (int s = 0; s < 6; ++s) mat5_vec(Lm, cells[s], vars[s]);
+        } else {
+          for (int s = 0; s < 6; ++s)
+            for (int c = 0; c < 5; ++c) vars[s][c] = cells[s][c];
+        }
+        R vl[5], vr[5], sl[5], sr[5];
         for (int c = 0; c < 5; ++c) {
           R left[5], right[5];
-          for (int s = 0; s < 5; ++s) { left[s] = cells[s][c]; right[s] = cells[5 - s][c]; }
-          R sl, sr;
-          weno5_right_edge(left, !full, P.weno_eps, P.weno_p, Ql[c], sl);
-          weno5_right_edge(right, !full, P.weno_eps, P.weno_p, Qr[c], sr);
-          Dl[c] = sl * R(dn_scale);
-          Dr[c] = -sr * R(dn_scale);  // mirrored stencil: slope changes sign
+          for (int s = 0; s < 5; ++s) { left[s] = vars[s][c]; right[s] = vars[5 - s][c]; }
+          weno5_right_edge(left, !full, P.weno_eps, P.weno_p, vl[c], sl[c]);
+          weno5_right_edge(right, !full, P.weno_eps, P.weno_p, vr[c], sr[c]);
+        }
+        if (chr) {
+          R t[5];
+          mat5_vec(Rm, vl, Ql);
+          mat5_vec(Rm, vr, Qr);
+          mat5_vec(Rm, sl, t);
+          for (int c = 0; c < 5; ++c) sl[c] = t[c];
+          mat5_vec(Rm, sr, t);
+          for (int c = 0; c < 5; ++c) sr[c] = t[c];
+        } else {
+          for (int c = 0; c < 5; ++c) { Ql[c] = vl[c]; Qr[c] = vr[c]; }
+        }
+        for (int c = 0; c < 5; ++c) {
+          Dl[c] = sl[c] * R(dn_scale);
+          Dr[c] = -sr[c] * R(dn_scale);  // mirrored stencil: slope changes sign
         }
         compat_state(Ql, Qr, P.gamma, Q0);
         for (int c = 0; c < 5; ++c) {
@@ -827,19 +917,36 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
   for (int t = 0; t < N2; ++t)
     for (int a = 0; a < N1; ++a)
       for (int nn = -1; nn < Nn; ++nn) {
+        // the 5x5 faces around this one: nb[field][t2 row r][t1 position s]
+        R nb[30][5][5];
+        for (int r = 0; r < 5; ++r)
+          for (int s = 0; s < 5; ++s) {
+            int ijk[3];
+            f.cell(nn, a - 2 + s, t - 2 + r, ijk);
+            for (int fld = 0; fld < nfield; ++fld) nb[fld][r][s] = ff.at(fld, ijk);
+          }
+        // mode 2: every field group (Q0, dQ0/dn, Q_l, Q_r and their normal slopes)
+        // in the characteristic variables of this face's equilibrium state Q0
+        R Rt[5][5], Lt[5][5];
+        if (chr) {
+          R q0c[5];
+          for (int c = 0; c < 5; ++c) q0c[c] = nb[c][2][2];
+          euler_eigenvectors(q0c, P.gamma, Rt);
+          invert5(Rt, Lt);
+          for (int grp = 0; grp < nfield / 5; ++grp)
+            for (int r = 0; r < 5; ++r)
+              for (int s = 0; s < 5; ++s) {
+                R x[5], y[5];
+                for (int c = 0; c < 5; ++c) x[c] = nb[5 * grp + c][r][s];
+                mat5_vec(Lt, x, y);
+                for (int c = 0; c < 5; ++c) nb[5 * grp + c][r][s] = y[c];
+              }
+        }
         // gv/g1/g2[m][l][field]: value, d/dt1, d/dt2 at the Gauss point (m, l)
         R gv[2][2][30], g1[2][2][30], g2[2][2][30];
         for (int fld = 0; fld < nfield; ++fld) {
           LineAtGauss<R> rows[5];
-          for (int r = 0; r < 5; ++r) {
-            R line[5];
-            for (int s = 0; s < 5; ++s) {
-              int ijk[3];
-              f.cell(nn, a - 2 + s, t - 2 + r, ijk);
-              line[s] = ff.at(fld, ijk);
-            }
-            rows[r] = tangential_line(line, full, P.weno_eps, P.weno_p);
-          }
+          for (int r = 0; r < 5; ++r) rows[r] = tangential_line(nb[fld][r], full, P.weno_eps, P.weno_p);
           for (int m = 0; m < 2; ++m) {
             R rowv[5], rowd[5];
             for (int r = 0; r < 5; ++r) { rowv[r] = rows[r].val[m]; rowd[r] = rows[r].der[m]; }
@@ -851,6 +958,18 @@ static void face_fluxes(const Box<R>& b, int d, const R& dt, std::vector<R>& Fn,
               g1[m][l][fld] = along_d.val[l];
             }
           }
+        }
+        if (chr) {  // back to conservative variables at every Gauss point
+          for (int m = 0; m < 2; ++m)
+            for (int l = 0; l < 2; ++l)
+              for (int grp = 0; grp < nfield / 5; ++grp) {
+                R* arrs[3] = {gv[m][l] + 5 * grp, g1[m][l] + 5 * grp, g2[m][l] + 5 * grp};
+                for (R* v : arrs) {
+                  R y[5];
+                  mat5_vec(Rt, v, y);
+                  for (int c = 0; c < 5; ++c) v[c] = y[c];
+                }
+              }
         }
         R Fsum[5], dFsum[5];
         for (int c = 0; c < 5; ++c) Fsum[c] = dFsum[c] = R(0.0);
@@ -1213,7 +1332,7 @@ static int validate(const ref_params* p) {
   const int minp = 6;
   if (p->nx < minp || p->nz < minp || p->ny < minp) return -1;
   if (!(p->gamma > 1.0) || !(p->prandtl > 0.0) || !(p->mu_ref >= 0.0) || !(p->cfl > 0.0)) return -1;
-  if (p->mode != 0 && p->mode != 1) return -1;
+  if (p->mode < 0 || p->mode > 2) return -1;
   if (p->bc_y != 0 && p->bc_y != 1) return -1;
   if (!(p->bulk_momentum >= 0.0) || (p->bulk_momentum > 0.0 && p->body_force_x != 0.0)) return -1;
   return 0;
@@ -1497,6 +1616,17 @@ int hgks_ref_tangential_line(const double* v, int weno, double eps, int p, int g
   ref::LineAtGauss<double> r = ref::tangential_line(v, weno != 0, eps, p);
   *val = r.val[gp];
   *der = r.der[gp];
+  return 0;
+}
+
+// Right eigenvectors (R, row-major [5][5], columns for u - c, u, u, u, u + c) of
+// the normal Euler-flux Jacobian at the local-frame state Q, and L = R^{-1}.
+int hgks_ref_eigenvectors(const double* Q, double gamma, double* Rout, double* Lout) {
+  double Rm[5][5], Lm[5][5];
+  ref::euler_eigenvectors(Q, gamma, Rm);
+  ref::invert5(Rm, Lm);
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) { Rout[5 * i + j] = Rm[i][j]; Lout[5 * i + j] = Lm[i][j]; }
   return 0;
 }
 
