@@ -51,8 +51,16 @@ enum {
  * HGKS_MODE_WENOZ: WENO-Z reconstruction (weights of the Z type with exponent
  *   weno_p in 1..4 and epsilon weno_eps > 0) in the normal direction and along
  *   both tangential axes, and the full flux of Eq. (flux) integrated in time, with
- *   the artificial collision time of Sec. 3 (c_art >= 0; isotropic turbulence). */
-enum { HGKS_MODE_SMOOTH = 0, HGKS_MODE_WENOZ = 1 };
+ *   the artificial collision time of Sec. 3 (c_art >= 0; isotropic turbulence).
+ * HGKS_MODE_WENOZ_CHAR: as HGKS_MODE_WENOZ, with the WENO-Z reconstruction done
+ *   on characteristic variables omega = R^{-1} Q (the Remark of Sec. 2.1 on
+ *   non-smooth flows), R the right eigenvectors of the Jacobian of the
+ *   face-normal Euler flux: in the normal direction at the mean of the face's two
+ *   cells, in the tangential directions at the face's equilibrium state Q0 (all
+ *   four Gauss points and all reconstructed fields of the face).  More robust on
+ *   under-resolved shocklets (Ma_t around 1); no adjoint (HGKS_E_UNSUPPORTED from
+ *   hgks_step_vjp). */
+enum { HGKS_MODE_SMOOTH = 0, HGKS_MODE_WENOZ = 1, HGKS_MODE_WENOZ_CHAR = 2 };
 /* HGKS_PREC_F64: all arithmetic in FP64.
  * HGKS_PREC_F32FLUX: reconstruction and flux arithmetic in FP32 around FP64
  *   anchors, FP64 state and compensated accumulation of the flux divergence. */
@@ -128,6 +136,16 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
  * not exported).  Device [5][nz][ny][nx] each.  dt as for hgks_operator.  A parity aid; no
  * synchronization. */
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF);
+
+/* Face fluxes of the two wall faces of the channel (Sec. 3.3; isothermal walls
+ * in y): the y-face fluxes F^n and dF^n/dt of the state q_in at the bottom wall
+ * y = -1 (face -1/2) and the top wall y = +1 (face ny-1/2) of every (x, z)
+ * column, face averages in the global frame as hgks_face_flux gives them.  F and
+ * dF are device [2][5][nz][nx] (entry 0 bottom, 1 top).  With the interior faces
+ * telescoping in Eq. (finite), these are the only fluxes that change the box's
+ * momentum and energy besides the body force.  A parity aid; no synchronization.
+ * Errors: HGKS_E_INVALID_ARG for NULL pointers, HGKS_E_UNSUPPORTED without walls. */
+int hgks_wall_flux(hgks_handle* h, const double* q_in, double* F, double* dF);
 
 /* Adjoint of one two-stage step (Eq. (two-stage)) with the time step dt frozen
  * (dt > 0): given the state q_n the step starts from and the cotangent lam_np1 of

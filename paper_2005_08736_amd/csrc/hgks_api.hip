@@ -110,12 +110,13 @@ int validate(const hgks_params* p) {
   if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0)) return HGKS_E_INVALID_ARG;
   if (!(p->gamma > 1.0) || !(p->prandtl > 0.0) || !(p->mu_ref >= 0.0) || !(p->cfl > 0.0)) return HGKS_E_INVALID_ARG;
   if (p->mu_exp != 0.0 && !(p->T_ref > 0.0)) return HGKS_E_INVALID_ARG;
-  if (p->mode != HGKS_MODE_SMOOTH && p->mode != HGKS_MODE_WENOZ) return HGKS_E_INVALID_ARG;
+  if (p->mode != HGKS_MODE_SMOOTH && p->mode != HGKS_MODE_WENOZ && p->mode != HGKS_MODE_WENOZ_CHAR)
+    return HGKS_E_INVALID_ARG;
   if (p->precision != HGKS_PREC_F64 && p->precision != HGKS_PREC_F32FLUX) return HGKS_E_INVALID_ARG;
   if (p->bc_y != HGKS_BC_PERIODIC && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_INVALID_ARG;
   long long N = (long long)p->nx * p->ny * p->nz;
   if (N > (1LL << 31) - 1) return HGKS_E_INVALID_ARG;  // 32-bit cell counts in the launch grids
-  if (p->mode == HGKS_MODE_WENOZ) {
+  if (p->mode != HGKS_MODE_SMOOTH) {
     if (!(p->weno_eps > 0.0) || p->weno_p < 1 || p->weno_p > 4 || !(p->c_art >= 0.0)) return HGKS_E_INVALID_ARG;
   }
   if (!(p->stretch_b >= 0.0)) return HGKS_E_INVALID_ARG;
@@ -125,7 +126,7 @@ int validate(const hgks_params* p) {
   // the stretched mesh is the channel's wall-normal mesh; walls and stretching
   // are implemented for the smooth mode
   if (p->stretch_b > 0.0 && p->bc_y != HGKS_BC_WALL_ISOTHERMAL) return HGKS_E_UNSUPPORTED;
-  if (p->mode == HGKS_MODE_WENOZ && (p->bc_y != HGKS_BC_PERIODIC || p->stretch_b > 0.0)) return HGKS_E_UNSUPPORTED;
+  if (p->mode != HGKS_MODE_SMOOTH && (p->bc_y != HGKS_BC_PERIODIC || p->stretch_b > 0.0)) return HGKS_E_UNSUPPORTED;
   return HGKS_OK;
 }
 
@@ -217,18 +218,23 @@ TF* fl_dir(hgks_handle* h, int d) {
   return static_cast<TF*>(h->fl) + (size_t)d * 10 * h->geo.N;
 }
 
+// face fluxes of direction d of state src into the face-flux array fl, by the
+// kernel of the handle's mode (stage 2: time derivative only)
+template <typename TF>
+void mode_flux(hgks_handle* h, int d, bool stage2, const double* src, TF* fl, const int* stop) {
+  switch (h->p.mode) {
+    case HGKS_MODE_WENOZ: launch_flux_z(h->geo, d, stage2, src, fl, stop, &h->ctrl->dt, h->stream); break;
+    case HGKS_MODE_WENOZ_CHAR: launch_flux_zc(h->geo, d, stage2, src, fl, stop, &h->ctrl->dt, h->stream); break;
+    default: launch_flux_fused(h->geo, d, stage2, src, fl, stop, h->stream);
+  }
+}
+
 // fluxes of all three directions of state src into h->fl (stage 2: time derivative only)
 void all_fluxes(hgks_handle* h, const double* src, bool stage2, const int* stop) {
   for (int d = 0; d < 3; ++d) {
     bool on = prof_begin(h, stage2 ? HGKS_KCLASS_FLUX_STAGE2 : HGKS_KCLASS_FLUX_STAGE1);
-    const bool z = h->p.mode == HGKS_MODE_WENOZ;
-    if (f32(h)) {
-      if (z) launch_flux_z(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, &h->ctrl->dt, h->stream);
-      else launch_flux_fused(h->geo, d, stage2, src, fl_dir<float>(h, d), stop, h->stream);
-    } else {
-      if (z) launch_flux_z(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, &h->ctrl->dt, h->stream);
-      else launch_flux_fused(h->geo, d, stage2, src, fl_dir<double>(h, d), stop, h->stream);
-    }
+    if (f32(h)) mode_flux(h, d, stage2, src, fl_dir<float>(h, d), stop);
+    else mode_flux(h, d, stage2, src, fl_dir<double>(h, d), stop);
     prof_end(h, on);
   }
 }
@@ -408,7 +414,7 @@ int hgks_step(hgks_handle* h, int32_t nsteps, double dt, double* dt_taken) {
 
 int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, double* dL) {
   if (!h || !q_in || !L || !dL) return HGKS_E_INVALID_ARG;
-  if (h->p.mode == HGKS_MODE_WENOZ) {
+  if (h->p.mode != HGKS_MODE_SMOOTH) {
     // the full flux is integrated over the step: it needs dt
     if (!(dt > 0.0)) return HGKS_E_INVALID_ARG;
     launch_set_dt(h->ctrl, dt, h->stream);
@@ -424,19 +430,30 @@ int hgks_operator(hgks_handle* h, const double* q_in, double dt, double* L, doub
 int hgks_face_flux(hgks_handle* h, int32_t dir, const double* q_in, double dt, double* F, double* dF) {
   if (!h || !q_in || !F || !dF || dir < 0 || dir > 2) return HGKS_E_INVALID_ARG;
   const Geo& g = h->geo;
-  const bool z = h->p.mode == HGKS_MODE_WENOZ;
-  if (z) {
+  if (h->p.mode != HGKS_MODE_SMOOTH) {
     if (!(dt > 0.0)) return HGKS_E_INVALID_ARG;
     launch_set_dt(h->ctrl, dt, h->stream);
   }
   if (f32(h)) {
-    if (z) launch_flux_z(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, &h->ctrl->dt, h->stream);
-    else launch_flux_fused(g, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero, h->stream);
+    mode_flux(h, dir, false, q_in, fl_dir<float>(h, dir), &h->ctrl->zero);
     launch_export_flux(g, dir, fl_dir<float>(h, dir), F, dF, h->stream);
   } else {
-    if (z) launch_flux_z(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, &h->ctrl->dt, h->stream);
-    else launch_flux_fused(g, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero, h->stream);
+    mode_flux(h, dir, false, q_in, fl_dir<double>(h, dir), &h->ctrl->zero);
     launch_export_flux(g, dir, fl_dir<double>(h, dir), F, dF, h->stream);
+  }
+  return hip_status(hipGetLastError());
+}
+
+int hgks_wall_flux(hgks_handle* h, const double* q_in, double* F, double* dF) {
+  if (!h || !q_in || !F || !dF) return HGKS_E_INVALID_ARG;
+  if (!h->geo.wall_y) return HGKS_E_UNSUPPORTED;
+  const Geo& g = h->geo;
+  if (f32(h)) {
+    launch_flux_fused(g, 1, false, q_in, fl_dir<float>(h, 1), &h->ctrl->zero, h->stream);
+    launch_export_wall_flux(g, fl_dir<float>(h, 1), F, dF, h->stream);
+  } else {
+    launch_flux_fused(g, 1, false, q_in, fl_dir<double>(h, 1), &h->ctrl->zero, h->stream);
+    launch_export_wall_flux(g, fl_dir<double>(h, 1), F, dF, h->stream);
   }
   return hip_status(hipGetLastError());
 }
@@ -447,6 +464,7 @@ int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* la
   if (h->geo.wall_y || h->geo.stretch_y || h->geo.fx != 0.0 || h->mflux) return HGKS_E_UNSUPPORTED;
   // smooth mode: constant viscosity, FP64 or the FP32-flux form; mode Z: FP64
   if (h->p.mode == HGKS_MODE_SMOOTH && h->p.mu_exp != 0.0) return HGKS_E_UNSUPPORTED;
+  if (h->p.mode == HGKS_MODE_WENOZ_CHAR) return HGKS_E_UNSUPPORTED;
   if (h->p.mode == HGKS_MODE_WENOZ && f32(h)) return HGKS_E_UNSUPPORTED;
   const Geo& g = h->geo;
   hipStream_t st = h->stream;

@@ -23,6 +23,9 @@ template <typename TF>
 void launch_operator(const Geo& g, const TF* fl, double* L, double* dL, hipStream_t st);
 template <typename TF>
 void launch_export_flux(const Geo& g, int dir, const TF* fl, double* F, double* dF, hipStream_t st);
+// the y-face fluxes of the two wall rows (channel), from the y-direction flux array
+template <typename TF>
+void launch_export_wall_flux(const Geo& g, const TF* fl, double* F, double* dF, hipStream_t st);
 void launch_flux_fused(const Geo& g, int dir, bool stage2, const double* q, double* fl, const int* stop,
                        hipStream_t st);
 void launch_flux_fused(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop,
@@ -31,6 +34,11 @@ void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, double* 
                    hipStream_t st);
 void launch_flux_z(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop, const double* dtp,
                    hipStream_t st);
+// mode Z with WENO-Z in characteristic variables
+void launch_flux_zc(const Geo& g, int dir, bool stage2, const double* q, double* fl, const int* stop,
+                    const double* dtp, hipStream_t st);
+void launch_flux_zc(const Geo& g, int dir, bool stage2, const double* q, float* fl, const int* stop,
+                    const double* dtp, hipStream_t st);
 void launch_operator_vjp(const Geo& g, int dir, bool f32, const double* q, const double* A, const double* B,
                          double cLA, double cLB, double cDA, double cDB, double* G, double* lam, hipStream_t st);
 void launch_operator_vjp_z(const Geo& g, int dir, const double* q, const double* A, const double* B, double cLA,

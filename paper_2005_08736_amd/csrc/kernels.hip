@@ -220,7 +220,12 @@ __global__ void __launch_bounds__(256) stage2_kernel(Geo g, const double* __rest
                                                      const double* __restrict__ qn, double* __restrict__ qout,
                                                      Ctrl* ctrl, double* __restrict__ part,
                                                      double* __restrict__ mpart, int step) {
-  if (ctrl->flag) return;
+  // other blocks of this launch may raise the flag while it runs: the block reads
+  // it once, so that all its waves leave together or all reach the reduction
+  __shared__ int stop;
+  if (threadIdx.x == 0) stop = ctrl->flag;
+  __syncthreads();
+  if (stop) return;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const double dt = ctrl->dt;
   double speed = 0.0, sm = 0.0, ss = 0.0, sv = 0.0;
@@ -383,6 +388,30 @@ __global__ void __launch_bounds__(256) export_flux_kernel(Geo g, int dir, const 
   }
 }
 
+// Face fluxes of the two wall faces of every (x, z) column of the channel: F and
+// dF [2][5][nz][nx], entry 0 the bottom wall face (row -1/2, kept in its own
+// array), entry 1 the top wall face (row ny-1/2, stored at the top row's cells);
+// face averages in the global frame, the reference pressure restored in the
+// normal (y) momentum.
+template <typename TF>
+__global__ void __launch_bounds__(256) export_wall_flux_kernel(Geo g, const TF* __restrict__ fl,
+                                                               double* __restrict__ F, double* __restrict__ dF) {
+  const long long m = (long long)g.n[0] * g.n[2];
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m) return;
+  const int i = int(idx % g.n[0]), k = int(idx / g.n[0]);
+  const TF* bot = static_cast<const TF*>(g.fwall);
+  const long long top = (long long)i + (long long)(g.n[1] - 1) * g.stride[1] + (long long)k * g.stride[2];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double pref = c == 2 ? g.p_ref : 0.0;
+    F[(long long)c * m + idx] = double(bot[(long long)c * m + idx]) + pref;
+    dF[(long long)c * m + idx] = double(bot[(long long)(5 + c) * m + idx]);
+    F[(long long)(5 + c) * m + idx] = double(fl[(long long)c * g.N + top]) + pref;
+    dF[(long long)(5 + c) * m + idx] = double(fl[(long long)(5 + c) * g.N + top]);
+  }
+}
+
 __global__ void __launch_bounds__(256) copy_kernel(const double* __restrict__ src, double* __restrict__ dst, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long stride = (long long)gridDim.x * blockDim.x;
@@ -449,6 +478,13 @@ void launch_export_flux(const Geo& g, int dir, const TF* fl, double* F, double* 
 }
 template void launch_export_flux<double>(const Geo&, int, const double*, double*, double*, hipStream_t);
 template void launch_export_flux<float>(const Geo&, int, const float*, double*, double*, hipStream_t);
+
+template <typename TF>
+void launch_export_wall_flux(const Geo& g, const TF* fl, double* F, double* dF, hipStream_t st) {
+  export_wall_flux_kernel<TF><<<blocks_for((long long)g.n[0] * g.n[2]), 256, 0, st>>>(g, fl, F, dF);
+}
+template void launch_export_wall_flux<double>(const Geo&, const double*, double*, double*, hipStream_t);
+template void launch_export_wall_flux<float>(const Geo&, const float*, double*, double*, hipStream_t);
 
 void launch_copy(const double* src, double* dst, long long n, hipStream_t st) {
   long long b = (n + 255) / 256;

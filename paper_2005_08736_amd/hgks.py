@@ -23,7 +23,7 @@ HGKS_E_NONPHYSICAL = -3
 HGKS_E_UNSUPPORTED = -4
 HGKS_E_WORKSPACE = -5
 HGKS_NDIAG = 34
-MODE_SMOOTH, MODE_WENOZ = 0, 1
+MODE_SMOOTH, MODE_WENOZ, MODE_WENOZ_CHAR = 0, 1, 2
 PREC_F64, PREC_F32FLUX = 0, 1
 
 DIAG_NAMES = [
@@ -37,7 +37,7 @@ EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
     "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp", "hgks_dilatation_pdf",
-    "hgks_plane_profiles", "hgks_dilatation_slice",
+    "hgks_plane_profiles", "hgks_dilatation_slice", "hgks_wall_flux",
 ]
 PDF_MAX_BINS = 4096
 PROFILE_NAMES = ["rho", "U", "V", "W", "p", "T", "uu", "vv", "ww", "uv", "rhoU"]
@@ -98,6 +98,8 @@ def load():
     L.hgks_profile_enable.argtypes = [vp, ctypes.c_int]
     L.hgks_profile_read.restype = ctypes.c_int
     L.hgks_profile_read.argtypes = [vp, D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    L.hgks_wall_flux.restype = ctypes.c_int
+    L.hgks_wall_flux.argtypes = [vp, vp, vp, vp]
     L.hgks_step_vjp.restype = ctypes.c_int
     L.hgks_step_vjp.argtypes = [vp, vp, dbl, vp, vp]
     L.hgks_dilatation_pdf.restype = ctypes.c_int
@@ -185,6 +187,17 @@ class Solver:
         _check(load().hgks_face_flux(self._h, int(direction), ctypes.c_void_p(q_in.data_ptr()), float(dt),
                                      ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(dF.data_ptr())),
                "hgks_face_flux")
+        return F, dF
+
+    def wall_flux(self, q_in: torch.Tensor | None = None):
+        """Face fluxes (F, dF) of the channel's wall faces (hgks_wall_flux): device
+        tensors [2, 5, nz, nx], entry 0 the bottom wall, 1 the top wall."""
+        q_in = self.q if q_in is None else q_in
+        shape = (2, 5, self.params["nz"], self.params["nx"])
+        F = torch.empty(shape, dtype=torch.float64, device=self.q.device)
+        dF = torch.empty(shape, dtype=torch.float64, device=self.q.device)
+        _check(load().hgks_wall_flux(self._h, ctypes.c_void_p(q_in.data_ptr()), ctypes.c_void_p(F.data_ptr()),
+                                     ctypes.c_void_p(dF.data_ptr())), "hgks_wall_flux")
         return F, dF
 
     def step_vjp(self, q_n: torch.Tensor, dt: float, lam_np1: torch.Tensor) -> torch.Tensor:

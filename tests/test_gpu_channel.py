@@ -266,3 +266,97 @@ def test_constant_bulk_momentum_periodic_mode_z():
         errs = rel_l2_fields(qd.cpu().numpy(), qr)
         assert max(errs) <= 1e-12, (i, errs)
     s.close()
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_channel_wall_flux_matches_oracle(case):
+    announce(f"channel wall flux {case}")
+    p, q = CASES[case]()
+    s = hgks.Solver(p, to_dev(q))
+    F, dF = s.wall_flux()
+    torch.cuda.synchronize()
+    Fr, dFr = oracle.wall_flux(p, q)
+    area = (p["lx"] / p["nx"]) * (p["lz"] / p["nz"])
+    Fr, dFr = Fr / area, dFr / area
+    F, dF = F.cpu().numpy(), dF.cpu().numpy()
+    # scales of the y-face fluxes of the whole box: at a no-slip wall dF^n/dt is
+    # zero up to the oracle's rounding of its moment algebra at T_w ~ 71
+    Fy_r, dFy_r = oracle.face_flux(p, q, 1)
+    scF, scD = np.abs(Fy_r).max() / area, np.abs(dFy_r).max() / area
+    assert np.abs(F - Fr).max() <= 1e-13 * scF, (np.abs(F - Fr).max(), scF)
+    assert np.abs(dF - dFr).max() <= 1e-11 * scD, (np.abs(dF - dFr).max(), scD)
+    # the exported top wall is the y-face row ny-1 of hgks_face_flux
+    Fy, dFy = s.face_flux(1)
+    assert torch.equal(torch.from_numpy(F[1]), Fy[:, :, -1, :].cpu())
+
+
+def test_channel_wall_flux_needs_walls():
+    p = cases.tgv_params(8)
+    s = hgks.Solver(p, to_dev(cases.tgv_state(8)))
+    with pytest.raises(hgks.HgksError) as e:
+        s.wall_flux()
+    assert e.value.status == hgks.HGKS_E_UNSUPPORTED
+
+
+def test_channel_x_momentum_budget_closes_every_step():
+    """The GPU step's x-momentum budget (Sec. 3.3; interior faces telescope in
+    Eq. (finite)): over each step the box's x-momentum changes by the
+    trapezoidal body-force input minus the time integral of the wall faces'
+    x-momentum flux, dt W(Q^n) + dt^2/6 (dW(Q^n) + 2 dW(Q*)), all taken from the
+    device (wall fluxes by hgks_wall_flux, Q* from hgks_operator), to round-off
+    of the momentum sum; five CFL steps of the stretched 32^3 channel."""
+    n, steps = 32, 5
+    announce(f"channel x-momentum budget {n}^3, {steps} steps")
+    p = cases.channel_params(n, n, n)
+    q = cases.channel_state(p, seed=3)
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    yf, _ = cases.channel_y(n, p["stretch_b"])
+    V = torch.from_numpy((p["lx"] / n) * (p["lz"] / n) * np.diff(yf)[None, :, None]).to(dev())
+    area = (p["lx"] / n) * (p["lz"] / n)
+    for i in range(steps):
+        q0 = qd.clone()
+        dt = s.step(1, return_dt=True)[0]
+        L, dL = s.operator(q0)
+        qs = q0 + 0.5 * dt * L + 0.125 * dt * dt * dL
+        _, dFs = s.wall_flux(qs)
+        Fn, dFn = s.wall_flux(q0)
+        torch.cuda.synchronize()
+        W = lambda F: float(torch.sum(F[1, 1] - F[0, 1])) * area
+        walls = dt * W(Fn) + dt * dt / 6.0 * (W(dFn) + 2.0 * W(dFs))
+        forcing = float(torch.sum(0.5 * dt * (qd[0] + q0[0]) * p["body_force_x"] * V))
+        change = float(torch.sum(qd[1] * V) - torch.sum(q0[1] * V))
+        scale = float(torch.sum(torch.abs(q0[1]) * V))
+        resid = change - (forcing - walls)
+        announce(f"  step {i}: residual {resid:.2e} (forcing {forcing:.3e}, walls {walls:.3e}, sum {scale:.3e})")
+        assert abs(resid) <= 1e-14 * scale, (i, resid, forcing, walls)
+
+
+def test_channel_fp32_form_against_oracle():
+    """The FP32-flux form against the FP64 oracle on the channel (Sec. 3.3) at
+    32^3, 100 steps with the oracle's time steps: relative L2 of every field and
+    the relative error of each diagnostic the stretched mesh defines, stated,
+    against the form's contract of 1e-5."""
+    n, steps, chunk = 32, 100, 20
+    announce(f"channel FP32 form vs oracle {n}^3, {steps} steps")
+    p = cases.channel_params(n, n, n)
+    q = cases.channel_state(p, seed=3)
+    p32 = dict(p, precision=hgks.PREC_F32FLUX)
+    qd = to_dev(q)
+    s = hgks.Solver(p32, qd)
+    qr = q.copy()
+    for c in range(steps // chunk):
+        qr, dts = oracle.step(p, qr, chunk)
+        for dt in dts:
+            s.step(1, dt=float(dt))
+        errs = rel_l2_fields(qd.cpu().numpy(), qr)
+        announce(f"  step {(c + 1) * chunk}: field rel L2 {['%.2e' % e for e in errs]}")
+        assert max(errs) <= 1e-5, ((c + 1) * chunk, errs)
+    d = s.diagnostics()
+    dr = oracle.diagnostics(p, qr)
+    keys = ("mass", "mom_x", "energy", "E_k", "rho_rms", "u_rms", "Ma_t", "min_rho", "min_p", "K", "rho_mean",
+            "c_mean", "volume", "max_speed")
+    rel = {k: abs(d[k] - dr[k]) / abs(dr[k]) for k in keys}
+    announce("  diagnostics rel err " + ", ".join(f"{k} {v:.1e}" for k, v in rel.items()))
+    for k in keys:
+        assert rel[k] <= 1e-5, (k, rel[k])
