@@ -1,0 +1,177 @@
+"""GPU parity of mode Z with WENO-Z in characteristic variables
+(HGKS_MODE_WENOZ_CHAR; the Remark of Sec. 2.1 on non-smooth flows) against the
+FP64 oracle's mode 2: face fluxes, the operator, per-step stepping (the
+isotropic field at Ma_t = 0.5 on 32^3 and, in the shocklet regime Ma_t = 1.0, on
+48^3, where conservative WENO-Z fails at once, and on 64^3), uniform flow,
+conservation, and the FP32-flux form against the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_08736_amd import cases, hgks
+from tests.test_gpu_parity import face_area, rel_l2_fields, smooth_field
+
+pytestmark = pytest.mark.gpu
+MODE = hgks.MODE_WENOZ_CHAR
+
+
+def dev():
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    return torch.device("cuda:0")
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(q):
+    return torch.from_numpy(np.ascontiguousarray(q)).to(dev())
+
+
+def ragged_c(q, **kw):
+    nz, ny, nx = q.shape[1:]
+    base = dict(nx=nx, ny=ny, nz=nz, lx=2 * math.pi, ly=1.3 * math.pi, lz=0.9 * math.pi,
+                mu_ref=3e-3, T_ref=0.8, mu_exp=0.76, prandtl=0.7, gamma=1.4, mode=MODE)
+    base.update(kw)
+    return cases.params(**base)
+
+
+CASES = {
+    "iso16_ma05": lambda: (cases.isotropic_params(16, 0.5, mode=MODE), cases.isotropic_state(16, 0, 0.5)),
+    # (Ma_t = 1.0 on 16^3 reconstructs to negative pressures in the oracle too)
+    "iso16_ma07_mu_const": lambda: (cases.isotropic_params(16, 0.7, mode=MODE, mu_exp=0.0),
+                                    cases.isotropic_state(16, 1, 0.7)),
+    "ragged13x9x7": lambda: (lambda q: (ragged_c(q), q))(smooth_field(13, 9, 7, seed=41, amp=0.2)),
+    "min6": lambda: (lambda q: (ragged_c(q), q))(smooth_field(6, 6, 6, seed=42, amp=0.2)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_zc_face_flux_matches_oracle(case, direction):
+    announce(f"characteristic mode Z face_flux {case} dir={direction}")
+    p, q = CASES[case]()
+    dt = oracle.cfl_dt(p, q)
+    s = hgks.Solver(p, to_dev(q))
+    F, dF = s.face_flux(direction, dt=dt)
+    torch.cuda.synchronize()
+    Fr, dFr = oracle.face_flux(p, q, direction, dt)
+    area = face_area(p, direction)
+    Fr, dFr = Fr / area, dFr / area
+    F, dF = F.cpu().numpy(), dF.cpu().numpy()
+    scF, scD = np.abs(Fr).max(), np.abs(dFr).max()
+    for k in range(5):
+        assert np.abs(F[k] - Fr[k]).max() <= 1e-13 * scF, (k, np.abs(F[k] - Fr[k]).max(), scF)
+        assert np.abs(dF[k] - dFr[k]).max() <= 1e-10 * scD, (k, np.abs(dF[k] - dFr[k]).max(), scD)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_zc_operator_matches_oracle(case):
+    announce(f"characteristic mode Z operator {case}")
+    p, q = CASES[case]()
+    dt = oracle.cfl_dt(p, q)
+    s = hgks.Solver(p, to_dev(q))
+    L, dL = s.operator(dt=dt)
+    torch.cuda.synchronize()
+    Lr, dLr = oracle.operator(p, q, dt)
+    h = [p["lx"] / p["nx"], p["ly"] / p["ny"], p["lz"] / p["nz"]]
+    scF, scD = np.zeros(5), np.zeros(5)
+    for d in range(3):
+        Fr, dFr = oracle.face_flux(p, q, d, dt)
+        area = face_area(p, d)
+        scF = np.maximum(scF, np.abs(Fr / area).reshape(5, -1).max(axis=1) / h[d])
+        scD = np.maximum(scD, np.abs(dFr / area).reshape(5, -1).max(axis=1) / h[d])
+    for A, Ar, sc, tol in ((L.cpu().numpy(), Lr, scF, 1e-13), (dL.cpu().numpy(), dLr, scD, 1e-10)):
+        for k in range(5):
+            assert np.abs(A[k] - Ar[k]).max() <= tol * sc[k], (k, np.abs(A[k] - Ar[k]).max(), sc[k])
+
+
+def _step_parity(n, ma_t, seed, steps, with_fp32):
+    p = cases.isotropic_params(n, ma_t, mode=MODE)
+    q = cases.isotropic_state(n, seed, ma_t)
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    q32 = to_dev(q)
+    s32 = hgks.Solver(dict(p, precision=hgks.PREC_F32FLUX), q32) if with_fp32 else None
+    qr = q.copy()
+    done = 0
+    for i in range(steps):
+        try:
+            qr, dtr = oracle.step(p, qr, 1)
+        except RuntimeError as e:  # the oracle reports a non-physical state (code -3)
+            assert "code -3" in str(e), e
+            st = s.step_status(1)
+            announce(f"  step {i}: non-physical in the oracle and on the device ({st})")
+            assert st == hgks.HGKS_E_NONPHYSICAL
+            break
+        dtr = float(dtr[0])
+        dts = s.step(1, return_dt=True)
+        assert abs(dts[0] - dtr) <= 1e-14 * dtr, (i, dts[0], dtr)
+        errs = rel_l2_fields(qd.cpu().numpy(), qr)
+        msg = f"  step {i}: FP64 max rel L2 {max(errs):.2e}"
+        if s32 is not None:
+            s32.step(1, dt=dtr)
+            e32 = rel_l2_fields(q32.cpu().numpy(), qr)
+            msg += f"; FP32 form {max(e32):.2e}"
+            assert max(e32) <= 1e-5, (i, e32)
+        announce(msg)
+        assert max(errs) <= 1e-12, (i, errs)
+        done += 1
+    return done
+
+
+def test_zc_iso32_steps_match_oracle_every_step():
+    announce("characteristic mode Z isotropic 32^3 Ma_t 0.5, 6 steps (FP64 and FP32 form)")
+    assert _step_parity(32, 0.5, 0, 6, True) == 6
+
+
+def test_zc_iso48_shocklet_regime_steps_match_oracle():
+    """Ma_t = 1.0 on 48^3: conservative-variable WENO-Z gives a non-physical state
+    in the first step (oracle and device alike); the characteristic variant steps."""
+    announce("characteristic mode Z isotropic 48^3 Ma_t 1.0 seed 1, 4 steps")
+    p1 = cases.isotropic_params(48, 1.0)
+    q = cases.isotropic_state(48, 1, 1.0)
+    s1 = hgks.Solver(p1, to_dev(q))
+    assert s1.step_status(1) == hgks.HGKS_E_NONPHYSICAL
+    assert oracle.step_rc(p1, q, 1) == -3
+    assert _step_parity(48, 1.0, 1, 4, False) == 4
+
+
+def test_zc_iso64_shocklet_regime_steps_match_oracle():
+    announce("characteristic mode Z isotropic 64^3 Ma_t 1.0 seed 1, up to 20 steps (FP64 and FP32 form)")
+    done = _step_parity(64, 1.0, 1, 20, True)
+    announce(f"  {done} physical steps")
+    assert done >= 8  # conservative WENO-Z fails at step 7 on this field
+
+
+def test_zc_uniform_flow_bitwise_and_conservation():
+    announce("characteristic mode Z uniform flow, conservation")
+    q = cases.uniform_state(16, 8, 12, rho=1.3, vel=(0.4, -0.7, 0.25), p=0.9)
+    p = ragged_c(q)
+    qd = to_dev(q)
+    hgks.Solver(p, qd).step(3)
+    assert np.array_equal(qd.cpu().numpy(), q)
+    p = cases.isotropic_params(32, 0.5, mode=MODE)
+    q = cases.isotropic_state(32, 2, 0.5)
+    qd = to_dev(q)
+    hgks.Solver(p, qd).step(10)
+    q1 = qd.cpu().numpy()
+    scale = np.abs(q).reshape(5, -1).sum(axis=1)
+    scale[1:4] = np.sqrt(np.sum(q[1:4] ** 2, axis=0)).sum()
+    drift = np.abs(q1.reshape(5, -1).sum(axis=1) - q.reshape(5, -1).sum(axis=1)) / scale
+    assert np.all(drift <= 1e-13), drift
+
+
+def test_zc_has_no_adjoint():
+    p, q = CASES["min6"]()
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    with pytest.raises(hgks.HgksError) as e:
+        s.step_vjp(qd.clone(), 1e-3, torch.ones_like(qd))
+    assert e.value.status == hgks.HGKS_E_UNSUPPORTED
