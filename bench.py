@@ -31,13 +31,28 @@ PAPER_MCUPS_256 = 256 ** 3 / 9.09 / 1e6
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops of one face in the stage-1 flux kernel: normal
-# reconstruction + compatibility state + normal derivative (639) and tangential
-# reconstruction to four Gauss points + four gas-kinetic flux evaluations + face
-# average (2320), each face evaluated once.  Counted as executed FP64 VALU
-# operations (FMA = 2, SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes / faces) by rocprofv3
-# on the unfused kernels, where every face was computed exactly once.
-FLUX_STAGE1_FLOPS_PER_FACE = 639 + 2320
+# Algorithmic FP64 work of one face in the stage-1 flux kernel, by the scheme's
+# own operation count: the moment algebra of the gas-kinetic flux at four Gauss
+# points (~1.15k each), the tangential reconstruction to those points (~1.6k)
+# and the normal reconstruction with the compatibility state (~0.3k).  This is
+# the figure `frac` is priced on.
+FLUX_STAGE1_FLOPS_PER_FACE = 6500
+# The same face as this library evaluates it, in the closed form of the smooth
+# flux (Newtonian stress, Fourier heat flux and the Euler flux Jacobian instead of
+# the moment algebra): normal reconstruction + compatibility state + normal
+# derivative (639) and tangential reconstruction + four flux evaluations + face
+# average (2320), counted as executed FP64 operations (FMA = 2) by rocprofv3 on
+# unfused kernels that computed every face once.  Reported as `frac_closed_form`.
+FLUX_STAGE1_CLOSED_FORM_FLOPS_PER_FACE = 639 + 2320
+# Executed FP64 operations per face of the fused stage-1 kernels as they run
+# (halo recomputation included; mean of the three directions, FMA = 2), from
+# rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 for the sources with the digest below.
+# Reported as `frac_executed`: the share of the FMA peak the kernel issues.
+FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE = (2505 + 2417 + 2417) / 3
+# Mode Z (WENO-Z reconstruction, full flux integrated over the step): the
+# scheme's count per cell-update, about 1e5 FP64 operations over the two stages
+# and three directions, i.e. 1e5 / 6 per face and stage.
+FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # HBM bytes per face of the stage-1 flux kernel (mean of the three directions)
 # from two rocprofv3 --pmc passes, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the
 # factors make the same counters read the known 671 MB in / 671 MB out of the
@@ -186,11 +201,79 @@ def adjoint_modez_timing(reps, torch, cases, hgks, dev):
     return out
 
 
+def shocklet_run(args, torch, np, cases, hgks, dev, mode, n=256, ma_t=1.0, seed=0):
+    """The shocklet regime of Sec. 3.4: isotropic turbulence at Ma_t = 1.0, 256^3,
+    mode Z (conservative or characteristic WENO-Z), args.shocklet_steps CFL steps
+    in FP64 (one timed call), then the FP32-flux form along the same time steps
+    (one call per step, timed as a whole); Mcell-updates/s of both, the FP32
+    form's relative L2 against the FP64 state, or the step at which a form
+    reports a non-physical state."""
+    steps = args.shocklet_steps
+    name = "characteristic" if mode == hgks.MODE_WENOZ_CHAR else "conservative"
+    log(f"[bench] isotropic {n}^3 Ma_t {ma_t} seed {seed}, {name} WENO-Z")
+    q0 = cases.isotropic_state(n, seed, ma_t)
+    p = dict(cases.isotropic_params(n, ma_t, mode=mode))
+    N = n ** 3
+    out = {"workload": f"isotropic {n}^3, Ma_t {ma_t}, seed {seed}, mode Z with {name} WENO-Z, {steps} CFL steps",
+           "steps": steps}
+    a = torch.from_numpy(q0).to(dev)
+    s = hgks.Solver(p, a)
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        dts = s.step(steps, return_dt=True)
+    except hgks.HgksError as e:
+        if e.status != hgks.HGKS_E_NONPHYSICAL:
+            raise
+        out["fp64_nonphysical_at_step"] = s.failed_step()
+        log(f"[bench] shocklet run FP64: non-physical state at step {s.failed_step()}")
+        s.close()
+        return out
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    s.close()
+    ms1, c1 = prof["flux_stage1"]
+    ach = FLUX_Z_FLOPS_PER_FACE * N / (ms1 / max(c1, 1) / 1e3) / 1e12
+    out["fp64"] = {"value": N * steps / el / 1e6, "unit": UNIT, "ms_per_step": el / steps * 1e3,
+                   "dt_first": dts[0], "dt_last": dts[-1], "flux_stage1_avg_launch_ms": ms1 / max(c1, 1),
+                   "flux_roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
+                                     "flop_per_face": FLUX_Z_FLOPS_PER_FACE}}
+    log(f"[bench] shocklet FP64: {el / steps * 1e3:.2f} ms/step, {out['fp64']['value']:.1f} Mcell-updates/s")
+    b = torch.from_numpy(q0).to(dev)
+    s32 = hgks.Solver(dict(p, precision=hgks.PREC_F32FLUX), b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, dt in enumerate(dts):
+        if s32.step_status(1, dt=float(dt)) != hgks.HGKS_OK:
+            out["fp32_nonphysical_at_step"] = i
+            log(f"[bench] shocklet run FP32 form: non-physical state at step {i}")
+            s32.close()
+            return out
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t0
+    s32.close()
+    A, B = a.cpu().numpy(), b.cpu().numpy()
+    mom = float(np.sqrt(np.sum(A[1:4] ** 2)))
+    rel = [float(np.linalg.norm(B[k] - A[k])) / (mom if 1 <= k <= 3 else float(np.linalg.norm(A[k])))
+           for k in range(5)]
+    out["fp32_form"] = {"value": N * steps / el32 / 1e6, "unit": UNIT, "ms_per_step": el32 / steps * 1e3,
+                        "rel_l2_vs_fp64_per_field": rel, "rel_l2_vs_fp64": max(rel),
+                        "note": "same time steps as the FP64 run, one call per step"}
+    log(f"[bench] shocklet FP32 form: {el32 / steps * 1e3:.2f} ms/step, rel L2 vs FP64 {max(rel):.2e}")
+    return out
+
+
 def other_workloads(args, torch, np, cases, hgks, dev):
     """Throughput of the paper's other two workloads, each in its own solver:
     decaying isotropic turbulence at 256^3 (WENO-Z + full flux, mu ~ T^0.76,
-    Ma_t = 0.5, seed 0) in FP64 and the FP32-flux form, and the turbulent
-    channel at 128^3 (walls, tanh mesh, body force; FP64)."""
+    Ma_t = 0.5, seed 0) in FP64 and the FP32-flux form, the same at Ma_t = 1.0
+    (the shocklet regime) over a longer run, and the turbulent channel at 128^3
+    (walls, tanh mesh, body force; FP64)."""
     out = {}
 
     def timed(name, p, q0, steps):
@@ -210,6 +293,11 @@ def other_workloads(args, torch, np, cases, hgks, dev):
         n = p["nx"] * p["ny"] * p["nz"]
         r = {"value": n * steps / el / 1e6, "unit": UNIT, "ms_per_step": el / steps * 1e3, "steps": steps,
              "cells": n, "dt": dts[0], "flux_stage1_avg_launch_ms": ms1 / max(c1, 1)}
+        if p["mode"] != hgks.MODE_SMOOTH and p.get("precision", hgks.PREC_F64) == hgks.PREC_F64:
+            ach = FLUX_Z_FLOPS_PER_FACE * n / (ms1 / max(c1, 1) / 1e3) / 1e12
+            r["flux_roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
+                                  "flop_per_face": FLUX_Z_FLOPS_PER_FACE}
         log(f"[bench] {name}: {r['ms_per_step']:.2f} ms/step, {r['value']:.1f} Mcell-updates/s")
         s.close()
         return r, q
@@ -218,6 +306,7 @@ def other_workloads(args, torch, np, cases, hgks, dev):
     qi = cases.isotropic_state(256, 0, 0.5)
     pi = dict(cases.isotropic_params(256, 0.5))
     r64, a = timed("isotropic 256^3 mode Z FP64", pi, qi, args.other_steps)
+    pi["precision"] = hgks.PREC_F64
     pi32 = dict(pi)
     pi32["precision"] = hgks.PREC_F32FLUX
     r32, b = timed("isotropic 256^3 mode Z FP32 form", pi32, qi, args.other_steps)
@@ -229,6 +318,9 @@ def other_workloads(args, torch, np, cases, hgks, dev):
     r32["note"] = "each form takes its own CFL steps; the states are compared after the same number of steps"
     out["isotropic_256_modez_fp64"] = r64
     out["isotropic_256_modez_fp32"] = r32
+    if args.shocklet_steps > 0:
+        out["isotropic_256_modez_ma1"] = shocklet_run(args, torch, np, cases, hgks, dev, hgks.MODE_WENOZ)
+        out["isotropic_256_modez_char_ma1"] = shocklet_run(args, torch, np, cases, hgks, dev, hgks.MODE_WENOZ_CHAR)
     pc = dict(cases.channel_params(128, 128, 128))
     rc, _ = timed("channel 128^3 FP64", pc, cases.channel_state(pc, seed=0), 4 * args.other_steps)
     out["channel_128_fp64"] = rc
@@ -246,6 +338,8 @@ def main():
     ap.add_argument("--adjoint-reps", type=int, default=5)
     ap.add_argument("--other-steps", type=int, default=5,
                     help="timed steps of the isotropic (mode Z) and channel workloads (0: skip them)")
+    ap.add_argument("--shocklet-steps", type=int, default=100,
+                    help="CFL steps of the isotropic Ma_t = 1.0 run (0: skip it)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -314,9 +408,10 @@ def main():
     ms_flux, cnt_flux = prof["flux_stage1"]
     avg_flux_s = ms_flux / max(cnt_flux, 1) / 1e3
     achieved = FLUX_STAGE1_FLOPS_PER_FACE * N / avg_flux_s / 1e12
-    traffic = None
-    if FLUX_STAGE1_HBM_BYTES_PER_FACE is not None and FLUX_COUNTERS_SOURCE_DIGEST == kernel_source_digest():
-        traffic = FLUX_STAGE1_HBM_BYTES_PER_FACE * N
+    closed = FLUX_STAGE1_CLOSED_FORM_FLOPS_PER_FACE * N / avg_flux_s / 1e12
+    counters_current = FLUX_COUNTERS_SOURCE_DIGEST == kernel_source_digest()
+    executed = FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE * N / avg_flux_s / 1e12 if counters_current else None
+    traffic = FLUX_STAGE1_HBM_BYTES_PER_FACE * N if counters_current else None
     roofline = {
         "bound": "alu",
         "kernel": "flux_fused (stage 1, FP64)",
@@ -326,6 +421,14 @@ def main():
         "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
         "traffic": traffic,
         "avg_launch_ms": avg_flux_s * 1e3,
+        "flop_per_face": FLUX_STAGE1_FLOPS_PER_FACE,
+        "frac_closed_form": closed / PEAK_FP64_VECTOR_TFLOPS,
+        "closed_form_flop_per_face": FLUX_STAGE1_CLOSED_FORM_FLOPS_PER_FACE,
+        "frac_executed": executed / PEAK_FP64_VECTOR_TFLOPS if executed is not None else None,
+        "executed_flop_per_face": FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE if counters_current else None,
+        "note": "frac prices each face at the scheme's operation count; frac_closed_form at the closed-form "
+                "smooth flux this kernel evaluates; frac_executed at the FP64 operations the kernel issues "
+                "(rocprofv3 counters)",
     }
     d = r64["solver"].diagnostics()
     log(f"[bench] after {args.warmup + args.steps} steps: E_k={d['E_k']:.8f} min_p={d['min_p']:.6f}")
@@ -344,7 +447,7 @@ def main():
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": value / PAPER_MCUPS_256 if n == 256 else None,
+        "vs_baseline": value / cpu["value"] if cpu else None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"taylor_green_{n}^3_fp64_smooth", "cells": N, "cfl": 0.4, "dt": dts[0],
@@ -357,6 +460,7 @@ def main():
         "paper_context": {"value": PAPER_MCUPS_256, "unit": UNIT, "workload": "Taylor-Green 256^3, FP64 (presumed)",
                           "hardware": "64 cores, Intel Xeon E5-2692 2.2 GHz (TianHe-II), MPI",
                           "source": "Sec. 3.2, Table time_table1: 9.09 s per step",
+                          "ratio": value / PAPER_MCUPS_256 if n == 256 else None,
                           "note": "another machine's figure: context, not the target"},
     }
     print(json.dumps(out), flush=True)

@@ -225,3 +225,49 @@ def test_z_fp32_form_against_fp64_path():
     q1 = b.cpu().numpy()
     drift = np.abs(q1.reshape(5, -1).sum(axis=1) - q.reshape(5, -1).sum(axis=1))
     assert np.all(drift <= 1e-13 * np.abs(q).reshape(5, -1).sum(axis=1) + 1e-13), drift
+
+
+# The isotropic workload of Sec. 3.4 at 64^3 (Table re72gridtable's smallest
+# grid): per-step parity of the FP64 path with the oracle at both turbulent Mach
+# numbers and both seeds, and the FP32-flux form with the same time steps
+# against the same oracle states.  If the oracle meets a non-physical state the
+# device must report it at the same step.
+@pytest.mark.parametrize("ma_t,seed,steps", [(0.5, 0, 20), (1.0, 1, 20), (0.5, 1, 3), (1.0, 0, 3)])
+def test_z_iso64_steps_match_oracle_every_step(ma_t, seed, steps):
+    n = 64
+    announce(f"mode Z isotropic {n}^3 Ma_t={ma_t} seed={seed}, {steps} steps (FP64 and FP32 form)")
+    p = cases.isotropic_params(n, ma_t)
+    q = cases.isotropic_state(n, seed, ma_t)
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    p32 = dict(p, precision=hgks.PREC_F32FLUX)
+    q32 = to_dev(q)
+    s32 = hgks.Solver(p32, q32)
+    qr = q.copy()
+    for i in range(steps):
+        try:
+            qr, dtr = oracle.step(p, qr, 1)
+        except RuntimeError as e:  # the oracle reports a non-physical state (code -3)
+            assert "code -3" in str(e), e
+            st = s.step_status(1)
+            announce(f"  step {i}: non-physical in the oracle and on the device ({st})")
+            assert st == hgks.HGKS_E_NONPHYSICAL
+            return
+        dtr = float(dtr[0])
+        dts = s.step(1, return_dt=True)
+        s32.step(1, dt=dtr)
+        assert abs(dts[0] - dtr) <= 1e-14 * dtr, (i, dts[0], dtr)
+        errs = rel_l2_fields(qd.cpu().numpy(), qr)
+        e32 = rel_l2_fields(q32.cpu().numpy(), qr)
+        announce(f"  step {i}: FP64 max rel L2 {max(errs):.2e}; FP32 form {max(e32):.2e}")
+        assert max(errs) <= 1e-12, (i, errs)
+        assert max(e32) <= 1e-5, (i, e32)
+    from tests.test_gpu_fp32 import check_diagnostics_against_oracle
+
+    d32, d64, dr = s32.diagnostics(), s.diagnostics(), oracle.diagnostics(p, qr)
+    scale_mom = float(np.sum(np.abs(qr[1:4]))) * (2 * math.pi / n) ** 3
+    for k in hgks.DIAG_NAMES:
+        err = abs(d64[k] - dr[k])
+        sc = scale_mom if k in ("mom_x", "mom_y", "mom_z") else abs(dr[k])
+        assert err <= 1e-11 * sc, (k, d64[k], dr[k])
+    check_diagnostics_against_oracle(d32, dr, f"FP32 form, isotropic {n}^3 after {steps} steps", scale_mom)
