@@ -168,6 +168,25 @@ int hgks_wall_flux(hgks_handle* h, const double* q_in, double* F, double* dF);
  * arrays hold zeros, not the step's face fluxes. */
 int hgks_step_vjp(hgks_handle* h, const double* q_n, double dt, const double* lam_np1, double* lam_n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): hgks_init + hgks_step +
+ * hgks_destroy in one call, with the workspace taken from a static device array
+ * of the library instead of the caller.  Arguments as for hgks_init (p, q,
+ * hip_stream) and hgks_step (nsteps, dt, dt_taken); the results are those of
+ * that sequence.  The array holds HGKS_STATIC_WORKSPACE_BYTES; parameters whose
+ * hgks_workspace_bytes exceeds it (about 400 bytes per cell in FP64, 280 in the
+ * FP32-flux form: up to ~160k cells) return HGKS_E_WORKSPACE before any device
+ * work.  Each device holds its own copy of the array from the first call made
+ * with that device current until the process ends; the call allocates and frees
+ * no device memory.  Every call on a device shares that device's copy, which
+ * keeps the last call's contents (each call resets the control block and writes
+ * every other part before reading it): calls that overlap on one device, from
+ * several threads or on several streams, race and must not be made.
+ * Synchronizes the stream. */
+#define HGKS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int hgks_step_static(const hgks_params* p, double* q, int32_t nsteps, double dt, double* dt_taken,
+                     void* hip_stream);
+
 /* Global FP64 diagnostics of the bound state (Sec. 3.1, 3.4): out (host) receives
  * HGKS_NDIAG doubles in this order:
  *   0..4 totals sum Q_k |Omega_i|; 5 E_k; 6 enstrophy zeta; 7 eps1; 8 eps2;

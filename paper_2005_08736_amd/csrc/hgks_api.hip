@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -11,6 +12,13 @@
 #include "internal.hpp"
 
 using namespace hgks;
+
+// Workspace of hgks_step_static: one file-scope device array, a copy of which
+// every device the library runs on holds for the life of the process.  Host
+// code never uses the array's name as an address (in host code it names a
+// host-side stand-in); it uses the device address hipGetSymbolAddress returns,
+// taken once per device with that device current (static_workspace below).
+static __device__ __align__(256) char scratch[HGKS_STATIC_WORKSPACE_BYTES];
 
 struct hgks_handle {
   hgks_params p;
@@ -277,9 +285,44 @@ void stage2(hgks_handle* h, const double* cur, double* other, int step) {
                                   h->stream);
 }
 
+constexpr size_t kStaticWorkspaceBytes = HGKS_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+
+// The calling thread's current device's copy of scratch, or nullptr if the
+// runtime cannot provide it.
+void* static_workspace() {
+  static std::once_flag once[kMaxDevices];
+  static void* addr[kMaxDevices];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::call_once(once[dev], [dev] {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) addr[dev] = ptr;
+  });
+  return addr[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+int hgks_step_static(const hgks_params* p, double* q, int32_t nsteps, double dt, double* dt_taken,
+                     void* hip_stream) {
+  int v = validate(p);
+  if (v != HGKS_OK) return v;
+  if (!q || nsteps < 0) return HGKS_E_INVALID_ARG;
+  if (layout_for(p).total > kStaticWorkspaceBytes) return HGKS_E_WORKSPACE;
+  void* ws = static_workspace();
+  if (!ws) return HGKS_E_DEVICE;
+  // hgks_init clears the control block; every other part of the workspace the
+  // step reads is written earlier in the same call
+  hgks_handle* h = nullptr;
+  int st = hgks_init(p, q, ws, kStaticWorkspaceBytes, hip_stream, &h);
+  if (st != HGKS_OK) return st;
+  st = hgks_step(h, nsteps, dt, dt_taken);
+  hgks_destroy(h);
+  return st;
+}
 
 size_t hgks_workspace_bytes(const hgks_params* p) {
   int v = validate(p);

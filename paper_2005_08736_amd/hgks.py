@@ -37,8 +37,9 @@ EXPORTED = [
     "hgks_workspace_bytes", "hgks_init", "hgks_step", "hgks_operator", "hgks_face_flux",
     "hgks_diagnostics", "hgks_failed_step", "hgks_destroy", "hgks_strerror",
     "hgks_profile_enable", "hgks_profile_read", "hgks_step_vjp", "hgks_dilatation_pdf",
-    "hgks_plane_profiles", "hgks_dilatation_slice", "hgks_wall_flux",
+    "hgks_plane_profiles", "hgks_dilatation_slice", "hgks_wall_flux", "hgks_step_static",
 ]
+STATIC_WORKSPACE_BYTES = 64 << 20
 PDF_MAX_BINS = 4096
 PROFILE_NAMES = ["rho", "U", "V", "W", "p", "T", "uu", "vv", "ww", "uv", "rhoU"]
 KCLASS_NAMES = ["dt", "flux_stage1", "flux_stage2", "stage1", "stage2", "operator_vjp"]
@@ -98,6 +99,8 @@ def load():
     L.hgks_profile_enable.argtypes = [vp, ctypes.c_int]
     L.hgks_profile_read.restype = ctypes.c_int
     L.hgks_profile_read.argtypes = [vp, D, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    L.hgks_step_static.restype = ctypes.c_int
+    L.hgks_step_static.argtypes = [P, vp, i32, dbl, D, vp]
     L.hgks_wall_flux.restype = ctypes.c_int
     L.hgks_wall_flux.argtypes = [vp, vp, vp, vp]
     L.hgks_step_vjp.restype = ctypes.c_int
@@ -127,6 +130,24 @@ def make_params(d: dict) -> HgksParams:
 
 def workspace_bytes(params: dict) -> int:
     return int(load().hgks_workspace_bytes(ctypes.byref(make_params(params))))
+
+
+def step_static(params: dict, q: torch.Tensor, nsteps: int = 1, dt: float = 0.0, return_dt: bool = False,
+                stream: torch.cuda.Stream | None = None):
+    """hgks_step_static: advance q (contiguous float64 device tensor [5, nz, ny,
+    nx], in place) by nsteps steps using the library's static device workspace
+    instead of an allocated one.  Returns the time steps when return_dt."""
+    if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous()):
+        raise ValueError("q must be a contiguous float64 device tensor")
+    if tuple(q.shape) != (5, params["nz"], params["ny"], params["nx"]):
+        raise ValueError(f"q has shape {tuple(q.shape)}, expected (5, nz, ny, nx)")
+    stream = stream if stream is not None else torch.cuda.current_stream(q.device)
+    buf = (ctypes.c_double * max(int(nsteps), 1))()
+    st = load().hgks_step_static(ctypes.byref(make_params(params)), ctypes.c_void_p(q.data_ptr()), int(nsteps),
+                                 float(dt), buf if return_dt else None, ctypes.c_void_p(stream.cuda_stream))
+    if st != HGKS_OK:
+        raise HgksError(st, "hgks_step_static")
+    return [buf[i] for i in range(int(nsteps))] if return_dt else None
 
 
 def _check(status: int, what: str):

@@ -94,3 +94,25 @@ def test_init_rejects_missing_small_or_misaligned_workspace():
     assert rc == hgks.HGKS_E_INVALID_ARG
     assert lib.hgks_init(ctypes.byref(prm), None, ctypes.c_void_p(1 << 21), need, None,
                          ctypes.byref(h)) == hgks.HGKS_E_INVALID_ARG
+
+
+def test_static_step_checks_its_limit_before_the_device():
+    """hgks_step_static validates the parameters and the size of its static
+    workspace on the host: an oversized box returns HGKS_E_WORKSPACE and a
+    negative step count HGKS_E_INVALID_ARG, without touching the device."""
+    import ctypes
+
+    lib = hgks.load()
+    fake_q = ctypes.c_void_p(1 << 20)
+    p = cases.tgv_params(64)
+    assert hgks.workspace_bytes(p) > hgks.STATIC_WORKSPACE_BYTES
+    assert lib.hgks_step_static(ctypes.byref(hgks.make_params(p)), fake_q, 1, 0.0, None,
+                                None) == hgks.HGKS_E_WORKSPACE
+    small = cases.tgv_params(16)
+    assert hgks.workspace_bytes(small) <= hgks.STATIC_WORKSPACE_BYTES
+    assert lib.hgks_step_static(ctypes.byref(hgks.make_params(small)), fake_q, -1, 0.0, None,
+                                None) == hgks.HGKS_E_INVALID_ARG
+    assert lib.hgks_step_static(ctypes.byref(hgks.make_params(small)), None, 1, 0.0, None,
+                                None) == hgks.HGKS_E_INVALID_ARG
+    assert lib.hgks_step_static(ctypes.byref(hgks.make_params(dict(small, nx=5))), fake_q, 1, 0.0, None,
+                                None) == hgks.HGKS_E_INVALID_ARG
