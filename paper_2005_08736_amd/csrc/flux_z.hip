@@ -61,43 +61,29 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   zgp_pair<T, DIR, false>(g, ff, ed, kZQ0 + 0, kZQ0 + 1, a, t, sm, sl, Q0[0], Q02[0], Q0[1], Q02[1], tok);
   zgp_pair<T, DIR, false>(g, ff, ed, kZQ0 + 2, kZQ0 + 3, a, t, sm, sl, Q0[2], Q02[2], Q0[3], Q02[3], tok);
   zgp_field<T, DIR, false>(g, ff, ed, kZQ0 + 4, a, t, sm, sl, Q0[4], dum, Q02[4], tok);
-  ZCoef<T> c;
-  zflux_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
-  ZAcc<T> acc;
-  {
-    T D[3][5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      zgp_pair<T, DIR, true>(g, ff, ed, kZDn + k, kZQ0 + k, a, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
-      D[2][k] = Q02[k];
-    }
-    zside(c.s0, D, 0, K, c.eq1, c.eqh, acc, true);
-  }
-  {
-    // the next side's LDS reads wait for the previous side's result
+  ZFold<T> c;
+  zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
+  ZOut<T> o;
+  // one side per trip of a loop that is not unrolled: the scheduler cannot
+  // overlap one side's reconstruction with another side's moments, and a single
+  // copy of the side's code holds its temporaries
+#pragma unroll 1
+  for (int side = 0; side < 3; ++side) {
+    // the side's LDS reads wait for the previous side's result
     int aa = a;
-    zdep(aa, acc.I1[4]);
+    if (side > 0) zdep(aa, o.F[4]);
+    const int fd = side == 0 ? kZDn : (side == 1 ? kZDl : kZDr);
+    const int fs = side == 0 ? kZQ0 : (side == 1 ? kZQl : kZQr);
     T D[3][5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      zgp_pair<T, DIR, true>(g, ff, ed, kZDl + k, kZQl + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
-      D[2][k] = Ql2[k];
+      zgp_pair<T, DIR, true>(g, ff, ed, fd + k, fs + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
+      D[2][k] = side == 0 ? Q02[k] : (side == 1 ? Ql2[k] : Qr2[k]);
     }
-    zside(c.sl, D, +1, K, c.in1, c.inh, acc, false);
-  }
-  {
-    int aa = a;
-    zdep(aa, acc.I1[4]);
-    T D[3][5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      zgp_pair<T, DIR, true>(g, ff, ed, kZDr + k, kZQr + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
-      D[2][k] = Qr2[k];
-    }
-    zside(c.sr, D, -1, K, c.in1, c.inh, acc, false);
+    zfold_side(c, side, D, K, dt, o);
   }
   T F[5], dF[5];
-  zflux_end(g, c, acc, dt, F, dF);
+  zfold_end(g, o, F, dF);
   // sum of the four Gauss points (adjacent lanes), face average = sum / 4
 #pragma unroll
   for (int k = 0; k < 5; ++k) {

@@ -279,15 +279,15 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   // the three states first (the collision time needs them); each side's
   // tangential derivatives are reconstructed again just before that side, which
   // keeps fewer values live than holding them from the first pass
-  ZCoef<T> c;
+  ZFold<T> c;
   {
     T Ql[5], Qr[5], Q0[5], unused[5];
     zc_group<T, DIR, false>(g, ff, lb, kZQl, ez, face, sm, sl, Ql, unused, unused);
     zc_group<T, DIR, false>(g, ff, lb, kZQr, ez, face, sm, sl, Qr, unused, unused);
     zc_group<T, DIR, false>(g, ff, lb, kZQ0, ez, face, sm, sl, Q0, unused, unused);
-    zflux_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
+    zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
   }
-  ZAcc<T> acc;
+  ZOut<T> o;
 #pragma unroll 1
   for (int side = 0; side < 3; ++side) {
     const int fs = side == 0 ? kZQ0 : (side == 1 ? kZQl : kZQr);
@@ -295,12 +295,10 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
     T D[3][5], unused[5];
     zc_group<T, DIR, true>(g, ff, lb, fs, ez, face, sm, sl, unused, D[1], D[2]);
     zc_group<T, DIR, false>(g, ff, lb, fd, ez, face, sm, sl, D[0], unused, unused);
-    if (side == 0) zside(c.s0, D, 0, K, c.eq1, c.eqh, acc, true);
-    else if (side == 1) zside(c.sl, D, +1, K, c.in1, c.inh, acc, false);
-    else zside(c.sr, D, -1, K, c.in1, c.inh, acc, false);
+    zfold_side(c, side, D, K, dt, o);
   }
   T F[5], dF[5];
-  zflux_end(g, c, acc, dt, F, dF);
+  zfold_end(g, o, F, dF);
   // sum of the four Gauss points (adjacent lanes), face average = sum / 4
 #pragma unroll
   for (int k = 0; k < 5; ++k) {

@@ -349,10 +349,10 @@ __host__ __device__ __forceinline__ ZPrim<T> zprim(const Geo& g, const T* dQ) {
 }
 
 // Time-integral coefficients over [0, delta]: eq[0..2] for the equilibrium side,
-// in[0..2] for the two initial sides.
+// in[0..2] for the two initial sides; e = exp(-delta/tau) given (ztime_e) or
+// computed (ztime).
 template <typename T>
-__host__ __device__ __forceinline__ void ztime(T delta, T tau, T* eq, T* in) {
-  T e = exp(-delta / tau);
+__host__ __device__ __forceinline__ void ztime_e(T delta, T tau, T e, T* eq, T* in) {
   T om = T(1) - e;
   eq[0] = delta - tau * om;
   eq[1] = T(2) * tau * tau * om - tau * delta * (T(1) + e);
@@ -360,6 +360,10 @@ __host__ __device__ __forceinline__ void ztime(T delta, T tau, T* eq, T* in) {
   in[0] = tau * om;
   in[1] = T(-2) * tau * tau * om + tau * delta * e;
   in[2] = -tau * tau * om;
+}
+template <typename T>
+__host__ __device__ __forceinline__ void ztime(T delta, T tau, T* eq, T* in) {
+  ztime_e(delta, tau, T(exp(-delta / tau)), eq, in);
 }
 
 // Accumulated time integrals: I = flux moments (<u ...>), J = density moments,
@@ -499,17 +503,6 @@ __host__ __device__ __forceinline__ void zflux_begin(const Geo& g, const T* dQ0,
   ztime(T(0.5) * dt, tau, c.eqh, c.inh);
 }
 
-// The same with a given collision time.
-template <typename T>
-__host__ __device__ __forceinline__ void zflux_begin_tau(const Geo& g, const T* dQ0, const T* dQl, const T* dQr,
-                                                         T tau, T dt, ZCoef<T>& c) {
-  c.s0 = zprim(g, dQ0);
-  c.sl = zprim(g, dQl);
-  c.sr = zprim(g, dQr);
-  ztime(dt, tau, c.eq1, c.in1);
-  ztime(T(0.5) * dt, tau, c.eqh, c.inh);
-}
-
 // With LIN (acc linear in the slopes, zside<true>) the constant p_ref is not
 // taken out of the normal-momentum flux: F and dF stay linear in acc.
 template <bool LIN = false, typename T>
@@ -526,21 +519,180 @@ __host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>&
   if (!LIN) F[1] = F[1] - T(g.p_ref);
 }
 
-// Full flux with a given collision time (host checks of the device math).
+// ---------------------------------------------------------------------------
+// The same flux with each part folded into F^n and dF^n/dt as soon as its
+// moments are formed (the forward kernels).  F = (4 I(dt/2) - I(dt))/dt and
+// dF = 4 (I(dt) - 2 I(dt/2))/dt^2 are linear in the time integrals, and so is the
+// Prandtl correction's heat flux (zheat), so every part c_j rho <u^p P_j psi>
+// goes straight into
+//   F  += rho kF_j <u P_j psi>,   kF_j = (4 c_j(dt/2) - c_j(dt)) / dt,
+//   dF += rho kD_j <u P_j psi>,   kD_j = 4 (c_j(dt) - 2 c_j(dt/2)) / dt^2,
+// with its heat flux about U0 summed in qF, qD.  Neither the four integrals
+// I, J over dt and dt/2 nor a side's six moment rows are held at once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ZOut {
+  T F[5], D[5], qF, qD;
+};
+
+// kF, kD of the equilibrium side (eq = true) or of an initial side, from the
+// collision time; the exponentials come from the caller (e1 = exp(-dt/tau),
+// eh = exp(-dt/(2 tau))).
+template <typename T>
+__host__ __device__ __forceinline__ void zfd_coef(T dt, T tau, T e1, T eh, bool eq, T* kF, T* kD) {
+  T k1[3], kh[3], unused[3];
+  if (eq) {
+    ztime_e(dt, tau, e1, k1, unused);
+    ztime_e(T(0.5) * dt, tau, eh, kh, unused);
+  } else {
+    ztime_e(dt, tau, e1, unused, k1);
+    ztime_e(T(0.5) * dt, tau, eh, unused, kh);
+  }
+  const T idt = T(1) / dt;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    kF[j] = (T(4) * kh[j] - k1[j]) * idt;
+    kD[j] = T(4) * (k1[j] - T(2) * kh[j]) * idt * idt;
+  }
+}
+
+// One part of one side: moment rows r0 (p = 0) and r1 (p = 1) with weights
+// wF = rho kF_j, wD = rho kD_j.
+template <typename T>
+__host__ __device__ __forceinline__ void zfold(T wF, T wD, const T* r0, const T* r1, T U0, T V0, T W0, ZOut<T>& o,
+                                               bool first) {
+  const T h = zheat(r1, r0, U0, V0, W0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    o.F[k] = first ? wF * r1[k] : o.F[k] + wF * r1[k];
+    o.D[k] = first ? wD * r1[k] : o.D[k] + wD * r1[k];
+  }
+  o.qF = first ? wF * h : o.qF + wF * h;
+  o.qD = first ? wD * h : o.qD + wD * h;
+}
+
+// One side (as zside), folded into o; (U0, V0, W0) is the velocity of Q0.
+template <typename T>
+__host__ __device__ __forceinline__ void zside_fold(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* kF,
+                                                    const T* kD, T U0, T V0, T W0, ZOut<T>& o, bool first) {
+  const T i2l = T(0.5) / s.lam;
+  ZGauss<T> G;
+  zmom_gauss(G.v, 6, s.V, i2l);
+  zmom_gauss(G.w, 6, s.W, i2l);
+  G.x1 = K * i2l;
+  G.x2 = K * (K + T(2)) * i2l * i2l;
+  T M[7];
+  zmom_gauss(M, 7, s.U, i2l);
+  const ZSlopeCoef<T> sc = zslope_coef(s.U, s.V, s.W, s.lam, i2l, K);
+  T ea[4][4];
+  {
+    T a[3][5];
+    const T ir = T(1) / s.rho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T b[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) b[k] = D[d][k] * ir;
+      zslope(b, s.U, s.V, s.W, sc, a[d]);
+    }
+    zexpect_slopes(a, G, ea);
+  }
+  // time slope: <(a.u + A) psi> = 0 over the full-space Maxwellian
+  T A[5];
+  {
+    T ra[5], unused[5], bt[5];
+    zrows<4, false>(M, ea, ra, unused);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) bt[k] = -ra[k];
+    zslope(bt, s.U, s.V, s.W, sc, A);
+  }
+  if (half != 0) zmom_half(M, s.U, s.lam, i2l, T(half));
+  const T wF1 = s.rho * kF[1], wD1 = s.rho * kD[1];
+  {
+    T r0[5], r1[5];
+    zrows<4, true>(M, ea, r0, r1);  // a.u
+    zfold(wF1, wD1, r0, r1, U0, V0, W0, o, first);
+  }
+  {
+    T eA[3][4], r0[5], r1[5];
+    zexpect_phi(A, G, eA);
+    zrows<3, true>(M, eA, r0, r1);  // A
+    zfold(s.rho * kF[2], s.rho * kD[2], r0, r1, U0, V0, W0, o, false);
+  }
+  {
+    T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
+    T r0[5], r1[5];
+    zrows<1, true>(M, e1, r0, r1);  // phi = 1
+    zfold(s.rho * kF[0], s.rho * kD[0], r0, r1, U0, V0, W0, o, false);
+  }
+}
+
+// F^n (without p_ref in its normal-momentum component) and dF^n/dt from o.
+template <typename T>
+__host__ __device__ __forceinline__ void zfold_end(const Geo& g, const ZOut<T>& o, T* F, T* dF) {
+  const T fix = T(g.pr_fix);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    F[k] = o.F[k];
+    dF[k] = o.D[k];
+  }
+  F[4] = F[4] + fix * o.qF;
+  dF[4] = dF[4] + fix * o.qD;
+  F[1] = F[1] - T(g.p_ref);
+}
+
+// States and collision time of zflux_begin for the folded form.
+template <typename T>
+struct ZFold {
+  ZPrim<T> s0, sl, sr;
+  T tau, e1, eh;
+};
+
+template <bool VAR_MU, typename T>
+__host__ __device__ __forceinline__ void zfold_begin(const Geo& g, const T* dQ0, const T* dQl, const T* dQr, T dt,
+                                                     ZFold<T>& c) {
+  c.s0 = zprim(g, dQ0);
+  c.sl = zprim(g, dQl);
+  c.sr = zprim(g, dQr);
+  T T0 = c.s0.p / c.s0.rho;
+  T mu = T(g.mu_ref);
+  if (VAR_MU) mu = mu * pow(T0 / T(g.T_ref), T(g.mu_exp));
+  c.tau = mu / c.s0.p + T(g.c_art) * fabs((c.sl.p - c.sr.p) / (c.sl.p + c.sr.p)) * dt;
+  c.e1 = exp(-dt / c.tau);
+  c.eh = exp(-(T(0.5) * dt) / c.tau);
+}
+
+// side 0: equilibrium, 1: left initial state (u > 0), 2: right (u < 0)
+template <typename T>
+__host__ __device__ __forceinline__ void zfold_side(const ZFold<T>& c, int side, const T (*D)[5], T K, T dt,
+                                                    ZOut<T>& o) {
+  T kF[3], kD[3];
+  zfd_coef(dt, c.tau, c.e1, c.eh, side == 0, kF, kD);
+  const ZPrim<T>& s = side == 0 ? c.s0 : (side == 1 ? c.sl : c.sr);
+  zside_fold(s, D, side == 0 ? 0 : (side == 1 ? +1 : -1), K, kF, kD, c.s0.U, c.s0.V, c.s0.W, o, side == 0);
+}
+
+// Full flux with a given collision time, in the folded form of the forward
+// kernels (host checks of the device math).
 template <typename T>
 __host__ __device__ __forceinline__ void full_flux_tau(const Geo& g, const T* dQ0, const T (*D0)[5], const T* dQl,
                                                        const T (*Dl)[5], const T* dQr, const T (*Dr)[5], T tau, T dt,
                                                        T* F, T* dF) {
   const T K = T(g.K);
-  ZCoef<T> c;
-  zflux_begin_tau(g, dQ0, dQl, dQr, tau, dt, c);
-  ZAcc<T> acc;
-  zside(c.s0, D0, 0, K, c.eq1, c.eqh, acc, true);
-  zdep(c.sl.rho, acc.I1[4]);
-  zside(c.sl, Dl, +1, K, c.in1, c.inh, acc, false);
-  zdep(c.sr.rho, acc.I1[4]);
-  zside(c.sr, Dr, -1, K, c.in1, c.inh, acc, false);
-  zflux_end(g, c, acc, dt, F, dF);
+  ZFold<T> c;
+  c.s0 = zprim(g, dQ0);
+  c.sl = zprim(g, dQl);
+  c.sr = zprim(g, dQr);
+  c.tau = tau;
+  c.e1 = exp(-dt / tau);
+  c.eh = exp(-(T(0.5) * dt) / tau);
+  ZOut<T> o;
+  zfold_side(c, 0, D0, K, dt, o);
+  zdep(c.sl.rho, o.F[4]);
+  zfold_side(c, 1, Dl, K, dt, o);
+  zdep(c.sr.rho, o.F[4]);
+  zfold_side(c, 2, Dr, K, dt, o);
+  zfold_end(g, o, F, dF);
 }
 
 }  // namespace hgks

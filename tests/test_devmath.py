@@ -2,6 +2,8 @@
 same headers the kernels use: the Gauss-point flux and compatibility state
 against the oracle, and the hand-written vector-Jacobian products against
 central differences of the forward functions (no GPU needed)."""
+import zlib
+
 import numpy as np
 import pytest
 
@@ -9,6 +11,14 @@ from tests import devmath
 
 GAMMA = 1.4
 rng = np.random.default_rng(11)
+
+
+@pytest.fixture(autouse=True)
+def _seed_per_test(request):
+    """Each test draws from its own stream, seeded by its id, so that its inputs
+    do not depend on which tests ran before it in the same process."""
+    global rng
+    rng = np.random.default_rng(zlib.crc32(request.node.nodeid.encode()))
 
 
 def cons(r, U, p, g=GAMMA):

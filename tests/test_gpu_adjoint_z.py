@@ -192,10 +192,11 @@ def test_z_tgv32_gradient_matches_central_differences():
         def cd(hh):
             return (J_of(U0 + hh * d) - J_of(U0 - hh * d)) / (2 * hh)
 
-        # the |.| kinks of the Z weights and of the collision time make the
-        # difference quotient converge at first order in h once it straddles
-        # them: h = 0.002 (a velocity change of ~1e-5 per cell) keeps that below
-        # 1e-7 (measured over h from 0.05 down to 0.0005)
+        # the |p_l - p_r| kink of the collision time (the Z weights' |b0 - b2|
+        # enters squared at p = 2, which is smooth) makes the difference
+        # quotient converge at first order in h once it straddles a tie:
+        # h = 0.002 (a velocity change of ~1e-5 per cell) keeps that below 1e-7
+        # (measured over h from 0.05 down to 0.0005)
         h = 0.002
         fd = (4 * cd(h / 2) - cd(h)) / 3
         rel = abs(gd - fd) / abs(fd)
