@@ -198,29 +198,52 @@ __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, int f0
 
 // Phase 3 for one field group at this lane's Gauss point: value, t2-derivative
 // and (with T1DER) t1-derivative, in conservative variables.
+//
+// The WENO-Z edges across the five t2 rows depend on the t1 Gauss point only,
+// so the two lanes of a face with the same t1 point (adjacent lanes, sl = -1 and
+// +1) split them: of the group's jobs (the five components' value rows, and with
+// T1DER their t1-derivative rows) each lane evaluates every other one and the
+// pair swaps edges with a lane shuffle.  The arithmetic of each job is the same
+// on either lane, so the results do not depend on the split.
 template <typename T, int DIR, bool T1DER>
 __device__ __forceinline__ void zc_group_gp(const Geo& g, const T* lb, const ZEig<T>& ez, int face, T sm, T sl,
                                             T* val, T* d1, T* d2) {
   using TG = ZTileGeom<DIR>;
   const T eps = T(g.weno_eps);
+  constexpr int J = T1DER ? 10 : 5;  // job j: component j % 5, t1-derivative rows if j >= 5
+  const int mine = sl > T(0) ? 1 : 0;
+  // row r of job j at this lane's t1 point
+  auto row = [&](int j, int r) {
+    const int li = zc_line(face, r, j % 5);
+    const T m = lb[3 * li], ea = lb[3 * li + 1], eb = lb[3 * li + 2];
+    return j >= 5 ? zpar_der(m, ea, eb, sm) : zpar_val(m, ea, eb, sm);
+  };
   T wv[5], w1[5], w2[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    T rv[5], rd[5];
+  for (int s2 = 0; s2 < (J + 1) / 2; ++s2) {
+    const int j0 = 2 * s2, j1 = (2 * s2 + 1 < J) ? 2 * s2 + 1 : 2 * s2;  // an odd count repeats the last job
+    const int jo = mine ? j1 : j0;                                       // this lane's job
+    T rv[5];
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
-      const int li = zc_line(face, r, k);
-      const T m = lb[3 * li], ea = lb[3 * li + 1], eb = lb[3 * li + 2];
-      rv[r] = zpar_val(m, ea, eb, sm);
-      if (T1DER) rd[r] = zpar_der(m, ea, eb, sm);
-    }
+    for (int r = 0; r < 5; ++r) rv[r] = row(jo, r);
     T ea, eb;
     weno_z_edges(rv, eps, g.weno_p, ea, eb);
-    wv[k] = zpar_val(rv[2], ea, eb, sl);
-    w2[k] = zpar_der(rv[2], ea, eb, sl);
-    if (T1DER) {
-      weno_z_edges(rd, eps, g.weno_p, ea, eb);
-      w1[k] = zpar_val(rd[2], ea, eb, sl);
+    const T pa = __shfl_xor(ea, 1), pb = __shfl_xor(eb, 1);
+    // edges of j0 and j1 on both lanes
+    const T ea0 = mine ? pa : ea, eb0 = mine ? pb : eb;
+    const T ea1 = mine ? ea : pa, eb1 = mine ? eb : pb;
+    const T m0 = row(j0, 2), m1 = row(j1, 2);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int jj = h ? j1 : j0;
+      if (h && j1 == j0) continue;
+      const T m = h ? m1 : m0, a = h ? ea1 : ea0, b = h ? eb1 : eb0;
+      if (jj < 5) {
+        wv[jj] = zpar_val(m, a, b, sl);
+        w2[jj] = zpar_der(m, a, b, sl);
+      } else {
+        w1[jj - 5] = zpar_val(m, a, b, sl);
+      }
     }
   }
   zright(ez, wv, val);
@@ -321,10 +344,15 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   }
 }
 
+// FP64 holds one wave per SIMD (its registers spill into AGPRs there); the FP32
+// form fits three
+#ifndef HGKS_ZCWAVES_F32
+#define HGKS_ZCWAVES_F32 3
+#endif
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
-__global__ void __launch_bounds__(256) flux_zc_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl,
-                                                      const int* __restrict__ stop, const double* __restrict__ dtp,
-                                                      int nt1, int nt2, int nper) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : HGKS_ZCWAVES_F32)))
+flux_zc_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
+               const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   if (*stop) return;
   flux_zc_body<T, DIR, STAGE2, VAR_MU>(g, q, fl, dtp, nt1, nt2, nper);
 }

@@ -13,6 +13,7 @@ import torch
 
 import oracle
 from paper_2005_08736_amd import cases, hgks
+from tests.test_gpu_modez import _window
 from tests.test_gpu_parity import face_area, rel_l2_fields, smooth_field
 
 pytestmark = pytest.mark.gpu
@@ -148,6 +149,45 @@ def test_zc_iso64_shocklet_regime_steps_match_oracle():
     done = _step_parity(64, 1.0, 1, 20, True)
     announce(f"  {done} physical steps")
     assert done >= 8  # conservative WENO-Z fails at step 7 on this field
+
+
+def test_zc_iso256_shocklet_full_size_sampled_step():
+    """One CFL step of the benchmarked shocklet box (256^3, Ma_t = 1.0, seed 0) in
+    the kernels and launch shapes of the full-size run, FP64 and the FP32-flux
+    form from the same state: the oracle checks dt on the whole box and Q^{n+1}
+    at sampled cells from 13^3 windows (the two-stage dependence radius is 6)."""
+    n = 256
+    announce("characteristic mode Z isotropic 256^3 Ma_t 1.0 sampled step (FP64 and FP32 form)")
+    p = cases.isotropic_params(n, 1.0, mode=MODE)
+    q = cases.isotropic_state(n, 0, 1.0)
+    qd = to_dev(q)
+    s = hgks.Solver(p, qd)
+    dts = s.step(1, return_dt=True)
+    dt_ref = oracle.cfl_dt(p, q)
+    assert abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
+    q1 = qd.cpu().numpy()
+    s.close()
+    q32 = to_dev(q)
+    s32 = hgks.Solver(dict(p, precision=hgks.PREC_F32FLUX), q32)
+    s32.step(1, dt=dts[0])
+    q1_32 = q32.cpu().numpy()
+    s32.close()
+    rng = np.random.default_rng(2561)
+    pts = [tuple(rng.integers(0, n, size=3)) for _ in range(6)] + [(0, 0, 0), (n - 1, n - 1, n - 1)]
+    h = 2 * math.pi / n
+    worst32 = 0.0
+    for c in pts:
+        win = _window(q, c, 6)
+        pw = cases.isotropic_params(13, 1.0, mode=MODE, lx=13 * h, ly=13 * h, lz=13 * h)
+        qw, _ = oracle.step(pw, win, 1, dt=dts[0])
+        ref = qw[:, 6, 6, 6]
+        sc = np.maximum(np.abs(ref), 1.0)
+        got = q1[:, c[2], c[1], c[0]]
+        assert np.all(np.abs(got - ref) <= 1e-13 * sc), (c, got - ref)
+        got32 = q1_32[:, c[2], c[1], c[0]]
+        worst32 = max(worst32, float(np.max(np.abs(got32 - ref) / sc)))
+    announce(f"  FP32 form, worst sampled error {worst32:.2e}")
+    assert worst32 <= 1e-6
 
 
 def test_zc_uniform_flow_bitwise_and_conservation():
