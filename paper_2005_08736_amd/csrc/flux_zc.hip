@@ -85,6 +85,20 @@ __device__ __forceinline__ void zright(const ZEig<T>& e, const T* w, T* x) {
   x[4] = e.H * sum - e.u * e.c * dif + e.hq2 * w[1] + e.v * w[2] + e.w * w[3];
 }
 
+// The eigen-structure of each of the tile's 64 faces, kept in LDS (nine values a
+// face) once phase 1 has written Q0: every line job of phase 2 reads its face's.
+constexpr int kZEigVals = 9;
+template <typename T>
+__device__ __forceinline__ void zeig_store(const ZEig<T>& e, T* p) {
+  p[0] = e.u; p[1] = e.v; p[2] = e.w; p[3] = e.c; p[4] = e.ic; p[5] = e.H; p[6] = e.b1; p[7] = e.b2; p[8] = e.hq2;
+}
+template <typename T>
+__device__ __forceinline__ ZEig<T> zeig_load(const T* p) {
+  ZEig<T> e;
+  e.u = p[0]; e.v = p[1]; e.w = p[2]; e.c = p[3]; e.ic = p[4]; e.H = p[5]; e.b1 = p[6]; e.b2 = p[7]; e.hq2 = p[8];
+  return e;
+}
+
 // Phase 1: face-field entries; the normal WENO-Z on characteristic variables.
 template <typename T, int DIR>
 __device__ __forceinline__ void zcface_field(const Geo& g, const double* __restrict__ q, T* ff, int on, int o1,
@@ -162,19 +176,23 @@ __device__ __forceinline__ void zcface_field(const Geo& g, const double* __restr
 constexpr int kZcLines = 64 * 5 * 5;
 __device__ __forceinline__ int zc_line(int face, int r, int k) { return (face * 5 + r) * 5 + k; }
 
-// Phase 2 for one field group (first LDS field f0): lines of the five t1-neighbours
-// of every face's five t2 rows, in that face's characteristic variables.
-template <typename T, int DIR>
-__device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, int f0, T* lb) {
+// Phase 2 for NG field groups (first LDS fields f0a, f0b, f0c) at once: lines of
+// the five t1-neighbours of every face's five t2 rows, in that face's
+// characteristic variables, group g into lb + g * 3 * kZcLines.  Several groups
+// per pass fill the 256 threads better: one group is 320 jobs (two rounds, the
+// second a quarter full), two are 640 (three rounds) and three 960 (four).
+template <typename T, int DIR, int NG>
+__device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const T* eg, int f0a, int f0b, int f0c,
+                                               T* lb) {
   using TG = ZTileGeom<DIR>;
   const T eps = T(g.weno_eps);
-  for (int j = threadIdx.x; j < 64 * 5; j += 256) {
-    const int face = j / 5, r = j % 5;
+  for (int j = threadIdx.x; j < NG * 64 * 5; j += 256) {
+    const int grp = j / (64 * 5), jj = j - grp * (64 * 5);
+    const int f0 = grp == 0 ? f0a : (grp == 1 ? f0b : f0c);
+    T* lg = lb + grp * (3 * kZcLines);
+    const int face = jj / 5, r = jj % 5;
     const int a = face % TG::B, t = face / TG::B;
-    T q0[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) q0[k] = ff[(kZQ0 + k) * TG::NFF + (t + 2) * TG::P + a + 2];
-    const ZEig<T> ez = zeig(g, q0);
+    const ZEig<T> ez = zeig_load(eg + face * kZEigVals);
     T w[5][5];  // [t1 position s][component]
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
@@ -189,9 +207,9 @@ __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, int f0
       T ea, eb;
       weno_z_edges(line, eps, g.weno_p, ea, eb);
       const int li = zc_line(face, r, k);
-      lb[3 * li] = w[2][k];
-      lb[3 * li + 1] = ea;
-      lb[3 * li + 2] = eb;
+      lg[3 * li] = w[2][k];
+      lg[3 * li + 1] = ea;
+      lg[3 * li + 2] = eb;
     }
   }
 }
@@ -259,22 +277,18 @@ __device__ __forceinline__ void zc_group_gp(const Geo& g, const T* lb, const ZEi
   }
 }
 
-template <typename T, int DIR, bool T1DER>
-__device__ __forceinline__ void zc_group(const Geo& g, const T* ff, T* lb, int f0, const ZEig<T>& ez, int face, T sm,
-                                         T sl, T* val, T* d1, T* d2) {
-  __syncthreads();  // the previous group's lines have been read
-  zc_group_lines<T, DIR>(g, ff, f0, lb);
-  __syncthreads();
-  zc_group_gp<T, DIR, T1DER>(g, lb, ez, face, sm, sl, val, d1, d2);
-}
-
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
 __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                              const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   using TG = ZTileGeom<DIR>;
   static_assert(TG::B * TG::B * 4 == 256, "four lanes per face");
+  // FP64 builds the three states' lines in one pass and each side's two groups
+  // in one pass (150 KB of LDS, one workgroup per CU at one wave per SIMD); the
+  // FP32 form builds one group per pass and keeps three workgroups per CU
+  constexpr int NGS = sizeof(T) == 8 ? 3 : 1;  // line buffers
   __shared__ T ff[TG::NF * TG::NFF];
-  __shared__ T lb[3 * kZcLines];
+  __shared__ T lb[NGS * 3 * kZcLines];
+  __shared__ T eg[64 * kZEigVals];
   const int tile = tile_of_block(nper);
   const int Nn = g.n[DIR];
   if (tile >= Nn * nt1 * nt2) return;  // whole workgroup leaves together
@@ -298,16 +312,33 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
 #pragma unroll
     for (int k = 0; k < 5; ++k) q0[k] = ff[(kZQ0 + k) * TG::NFF + (t + 2) * TG::P + a + 2];
     ez = zeig(g, q0);
+    if (gp == 0) zeig_store(ez, eg + face * kZEigVals);
   }
+  __syncthreads();
+  constexpr int L = 3 * kZcLines;
   // the three states first (the collision time needs them); each side's
   // tangential derivatives are reconstructed again just before that side, which
   // keeps fewer values live than holding them from the first pass
   ZFold<T> c;
   {
     T Ql[5], Qr[5], Q0[5], unused[5];
-    zc_group<T, DIR, false>(g, ff, lb, kZQl, ez, face, sm, sl, Ql, unused, unused);
-    zc_group<T, DIR, false>(g, ff, lb, kZQr, ez, face, sm, sl, Qr, unused, unused);
-    zc_group<T, DIR, false>(g, ff, lb, kZQ0, ez, face, sm, sl, Q0, unused, unused);
+    if constexpr (NGS == 3) {
+      zc_group_lines<T, DIR, 3>(g, ff, eg, kZQl, kZQr, kZQ0, lb);
+      __syncthreads();
+      zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, Ql, unused, unused);
+      zc_group_gp<T, DIR, false>(g, lb + L, ez, face, sm, sl, Qr, unused, unused);
+      zc_group_gp<T, DIR, false>(g, lb + 2 * L, ez, face, sm, sl, Q0, unused, unused);
+    } else {
+      const int fs[3] = {kZQl, kZQr, kZQ0};
+      T* out[3] = {Ql, Qr, Q0};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (i > 0) __syncthreads();  // the previous group's lines have been read
+        zc_group_lines<T, DIR, 1>(g, ff, eg, fs[i], 0, 0, lb);
+        __syncthreads();
+        zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, out[i], unused, unused);
+      }
+    }
     zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
   }
   ZOut<T> o;
@@ -316,8 +347,21 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
     const int fs = side == 0 ? kZQ0 : (side == 1 ? kZQl : kZQr);
     const int fd = side == 0 ? kZDn : (side == 1 ? kZDl : kZDr);
     T D[3][5], unused[5];
-    zc_group<T, DIR, true>(g, ff, lb, fs, ez, face, sm, sl, unused, D[1], D[2]);
-    zc_group<T, DIR, false>(g, ff, lb, fd, ez, face, sm, sl, D[0], unused, unused);
+    __syncthreads();  // the previous pass's lines have been read
+    if constexpr (NGS == 3) {
+      zc_group_lines<T, DIR, 2>(g, ff, eg, fs, fd, 0, lb);
+      __syncthreads();
+      zc_group_gp<T, DIR, true>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
+      zc_group_gp<T, DIR, false>(g, lb + L, ez, face, sm, sl, D[0], unused, unused);
+    } else {
+      zc_group_lines<T, DIR, 1>(g, ff, eg, fs, 0, 0, lb);
+      __syncthreads();
+      zc_group_gp<T, DIR, true>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
+      __syncthreads();
+      zc_group_lines<T, DIR, 1>(g, ff, eg, fd, 0, 0, lb);
+      __syncthreads();
+      zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, D[0], unused, unused);
+    }
     zfold_side(c, side, D, K, dt, o);
   }
   T F[5], dF[5];
