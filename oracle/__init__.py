@@ -49,6 +49,7 @@ def lib():
             "hgks_ref_set_threads": (i32, [i32]),
             "hgks_ref_cfl_dt": (i32, [P, _D, _D]),
             "hgks_ref_step": (i32, [P, _D, i32, dbl, _D]),
+            "hgks_ref_two_stage_linear": (i32, [P, _D, dbl, _D]),
             "hgks_ref_operator": (i32, [P, _D, dbl, _D, _D]),
             "hgks_ref_face_flux": (i32, [P, _D, i32, dbl, _D, _D]),
             "hgks_ref_wall_flux": (i32, [P, _D, dbl, _D, _D]),
@@ -121,6 +122,16 @@ def step(params: dict, q: np.ndarray, nsteps: int, dt: float = 0.0):
     _check(rc, "step")
     return q, dts[:nsteps]
 
+
+def two_stage_linear(params: dict, A: np.ndarray, q: np.ndarray, dt: float):
+    """One step of the two-stage time stepping with the operator replaced by the
+    linear map L(Q) = A Q per cell (dL/dt = A L): pins the stage formulas."""
+    q = np.ascontiguousarray(q, dtype=np.float64).copy()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    rc = lib().hgks_ref_two_stage_linear(ctypes.byref(make_params(params)), _p(A), float(dt), _p(q))
+    if rc != 0:
+        raise RuntimeError(f"hgks_ref_two_stage_linear failed with code {rc}")
+    return q
 
 def step_rc(params: dict, q: np.ndarray, nsteps: int, dt: float = 0.0) -> int:
     q = _arr(q).copy()

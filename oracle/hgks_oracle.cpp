@@ -1097,11 +1097,13 @@ static bool physical(const Box<R>& b) {
 //   (rho U)^{n+1} += dt/2 (rho^{n+1} + rho^n) f_x,  (rho E)^{n+1} += dt/2 ((rho U)^{n+1} + (rho U)^n) f_x,
 // with f_x the constant body_force_x, or, with bulk_momentum > 0, the value that
 // makes the box integral of (rho U)^{n+1} equal bulk_momentum |Omega|.
-template <class R>
-static void step(Box<R>& b, const R& dt) {
+// op(b, dt, L, dL) supplies the operator and its time derivative; step() passes
+// the scheme's (operator_L), the time-stepping pin a linear map.
+template <class R, class Op>
+static void step_with(Box<R>& b, const R& dt, Op&& op) {
   std::vector<R> L1, dL1, L2, dL2;
   std::vector<R> qn = b.q;
-  operator_L(b, dt, L1, dL1);
+  op(b, dt, L1, dL1);
   for (int c = 0; c < 5; ++c)
     for (int k = 0; k < b.n[2]; ++k)
       for (int j = 0; j < b.n[1]; ++j)
@@ -1109,7 +1111,7 @@ static void step(Box<R>& b, const R& dt) {
           size_t o = b.idx(c, i, j, k);
           b.q[o] = qn[o] + R(0.5) * dt * L1[o] + R(0.125) * dt * dt * dL1[o];
         }
-  operator_L(b, dt, L2, dL2);
+  op(b, dt, L2, dL2);
   for (int c = 0; c < 5; ++c)
     for (int k = 0; k < b.n[2]; ++k)
       for (int j = 0; j < b.n[1]; ++j)
@@ -1144,6 +1146,11 @@ static void step(Box<R>& b, const R& dt) {
           b.q[o4] = b.q[o4] + R(0.5) * dt * (b.q[o1] + mx_old) * fx;
         }
   }
+}
+
+template <class R>
+static void step(Box<R>& b, const R& dt) {
+  step_with(b, dt, [](Box<R>& bb, const R& d, std::vector<R>& L, std::vector<R>& dL) { operator_L(bb, d, L, dL); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1380,6 +1387,38 @@ int hgks_ref_step(const ref_params* p, double* q, int nsteps, double dt_fixed, d
       return -3;
     }
   }
+  ref::store(b, q, nullptr);
+  return 0;
+}
+
+// Test hook for the time stepping alone: one step of Eq. (two-stage) in which the
+// operator is the linear map L(Q) = A Q on each cell's five components and dL/dt
+// = A L(Q), its exact time derivative along dQ/dt = A Q (A [5][5] row-major);
+// the grid comes from p, whose forcing must be off.  q is [5][nz][ny][nx], in
+// place.
+int hgks_ref_two_stage_linear(const ref_params* p, const double* A, double dt, double* q) {
+  if (ref::validate(p) || p->body_force_x != 0.0 || p->bulk_momentum > 0.0) return -1;
+  ref::Box<double> b(*p);
+  b.load(q);
+  auto lin = [&](ref::Box<double>& bb, const double&, std::vector<double>& L, std::vector<double>& dL) {
+    L.assign(bb.q.size(), 0.0);
+    dL.assign(bb.q.size(), 0.0);
+    for (int k = 0; k < bb.n[2]; ++k)
+      for (int j = 0; j < bb.n[1]; ++j)
+        for (int i = 0; i < bb.n[0]; ++i) {
+          for (int c = 0; c < 5; ++c) {
+            double s = 0.0;
+            for (int e = 0; e < 5; ++e) s += A[5 * c + e] * bb.q[bb.idx(e, i, j, k)];
+            L[bb.idx(c, i, j, k)] = s;
+          }
+          for (int c = 0; c < 5; ++c) {
+            double s = 0.0;
+            for (int e = 0; e < 5; ++e) s += A[5 * c + e] * L[bb.idx(e, i, j, k)];
+            dL[bb.idx(c, i, j, k)] = s;
+          }
+        }
+  };
+  ref::step_with(b, dt, lin);
   ref::store(b, q, nullptr);
   return 0;
 }

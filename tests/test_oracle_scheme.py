@@ -96,6 +96,34 @@ def test_operator_mirror_symmetry(oracle_mod, mode):
         assert np.allclose(Am, ref, rtol=0, atol=1e-12 * np.abs(A).max())
 
 
+def test_two_stage_step_is_the_fourth_order_taylor_polynomial(oracle_mod):
+    """Eq. (two-stage) with dL/dt the exact time derivative of L: on a linear
+    system dQ/dt = A Q (L = A Q, dL/dt = A^2 Q) one step multiplies Q by the
+    degree-four Taylor polynomial of exp(dt A),
+        I + X + X^2/2 + X^3/6 + X^4/24,  X = dt A,
+    for any A.  The oracle's own stage
+    combination runs here with the operator replaced by A (a test hook), on
+    random 5 x 5 matrices with |X| ~ 1, where a wrong stage weight changes a
+    coefficient by a visible amount."""
+    rng = np.random.default_rng(23)
+    p = cases.params(nx=6, ny=6, nz=6, lx=1.0, ly=1.0, lz=1.0)
+    for trial in range(6):
+        A = rng.normal(size=(5, 5))
+        dt = 1.0 / np.linalg.norm(A, 2) * (0.5 + trial * 0.3)
+        q = rng.normal(size=(5, 6, 6, 6))
+        got = oracle_mod.two_stage_linear(p, A, q, dt)
+        X = dt * A
+        P = np.eye(5) + X + X @ X / 2 + X @ X @ X / 6 + X @ X @ X @ X / 24
+        want = np.einsum("ce,ekji->ckji", P, q)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), (trial, np.abs(got - want).max())
+    # the scalar case: the stability polynomial of the scheme on dQ/dt = z Q
+    for z in (-1.0, -2.5, 0.7):
+        A = z * np.eye(5)
+        q = np.ones((5, 6, 6, 6))
+        got = oracle_mod.two_stage_linear(p, A, q, 1.0)
+        assert np.allclose(got, 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24, rtol=1e-15, atol=1e-15), z
+
+
 def test_shear_wave_decays_at_the_viscous_rate(oracle_mod):
     # U = 0, V = A sin x, uniform rho, p: the Navier-Stokes equations reduce to the
     # heat equation for V, and the kinetic flux carries the stress mu dV/dx with
