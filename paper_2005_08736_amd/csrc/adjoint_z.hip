@@ -9,15 +9,15 @@
 //   A. recomputes the face field and the t1 edge values of the tile and its halo
 //      into LDS (the forward arithmetic, ztile.hpp);
 //   B. per Gauss point: recomputes the 60 reconstructed values the flux takes,
-//      forms the 10 x 60 Jacobian of the Gauss-point flux column block by column
-//      block with forward tangents (tangent.hpp) and multiplies its transpose into
-//      the point's cotangent; then transposes the tangential reconstruction of
-//      each of the 30 fields (parabolas and WENO-Z edge pairs, whose 2 x 5
-//      Jacobians come from tangents as well) into an LDS face-field cotangent
+//      takes the point's cotangent back through the Gauss-point flux with the
+//      hand-written reverse sweep (zreverse.hpp), then transposes the
+//      tangential reconstruction of each of the 30 fields (parabolas and WENO-Z
+//      edge pairs, reversed by hand as well) into an LDS face-field cotangent
 //      (LDS atomics);
 //   C. per face-field entry: reverses the compatibility state (by hand,
-//      adjoint_common.hpp) and the normal WENO-Z values and slopes, and adds the
-//      six cells' cotangents into lambda (device atomics).
+//      adjoint_common.hpp) and the normal WENO-Z values and slopes (by hand,
+//      zreverse.hpp), and adds the six cells' cotangents into lambda (device
+//      atomics).
 // Mixing the two cotangent sources mu = cA * A + cB * B inside the kernel lets one
 // launch per direction serve both stages of the step adjoint.  This path is
 // exact but not tuned: it is meant for the small boxes on which the mode-Z
@@ -29,17 +29,13 @@
 
 namespace hgks {
 
-// The flux Jacobian transpose (zflux_jt_values for the values, zflux_jt_slopes
-// for the slopes), kept out of line: one copy serves the three face directions.
+// The flux's vector-Jacobian product at one Gauss point (the hand-written
+// reverse of zreverse.hpp), kept out of line: one copy serves the three face
+// directions.
 template <bool VAR_MU>
-__device__ __noinline__ void zflux_jt_value_pass(const Geo& g, const double* X, double dt, const double* Fb,
-                                                 const double* dFb, double* Xb) {
-  zflux_jt_values<VAR_MU>(g, X, dt, Fb, dFb, Xb);
-}
-template <bool VAR_MU>
-__device__ __noinline__ void zflux_jt_slope_pass(const Geo& g, const double* X, double dt, const double* Fb,
-                                                 const double* dFb, double* Xb) {
-  zflux_jt_slopes<VAR_MU>(g, X, dt, Fb, dFb, Xb);
+__device__ __noinline__ void zflux_vjp_pass(const Geo& g, const double* X, double dt, const double* Fb,
+                                            const double* dFb, double* Xb) {
+  zflux_vjp<VAR_MU>(g, X, dt, Fb, dFb, Xb, kXQ0, kXQl, kXQr, kXD0, kXDl, kXDr);
 }
 
 // Transpose of zgp_field for field f at Gauss point (sm, sl) of the face at tile
@@ -65,22 +61,16 @@ __device__ __forceinline__ void zgp_field_vjp(const Geo& g, const double* ff, co
   double rvb[5] = {0, 0, 0, 0, 0}, rdb[5] = {0, 0, 0, 0, 0};
   {
     // val = rv2 + sl (B - A) G ;  d2 = ih2 ((B - A) + sl S3 (A + B - 2 rv2)),  (A, B) = edges(rv)
-    double J[2][5];
-    wze_jac(rv, eps, p, J);
     const double Ab = -sl * G * vb + ih2 * d2b * (sl * S3 - 1.0);
     const double Bb = sl * G * vb + ih2 * d2b * (sl * S3 + 1.0);
     rvb[2] += vb - 2.0 * sl * S3 * ih2 * d2b;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) rvb[i] += J[0][i] * Ab + J[1][i] * Bb;
+    weno_z_edges_vjp(rv, eps, p, Ab, Bb, rvb);
   }
   if (T1DER) {
     // d1 = ih1 (rd2 + sl (B' - A') G),  (A', B') = edges(rd)
-    double J[2][5];
-    wze_jac(rd, eps, p, J);
     const double Ab = -sl * G * ih1 * d1b, Bb = sl * G * ih1 * d1b;
     rdb[2] += ih1 * d1b;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) rdb[i] += J[0][i] * Ab + J[1][i] * Bb;
+    weno_z_edges_vjp(rd, eps, p, Ab, Bb, rdb);
   }
   // line r: rv = m + sm (eb - ea) G ;  rd = (eb - ea) + sm S3 (ea + eb - 2 m),  (ea, eb) = edges(line)
 #pragma unroll 1
@@ -93,10 +83,10 @@ __device__ __forceinline__ void zgp_field_vjp(const Geo& g, const double* ff, co
     double line[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) line[i] = src[i];
-    double J[2][5];
-    wze_jac(line, eps, p, J);
+    double lb[5] = {0.0, 0.0, mb, 0.0, 0.0};
+    weno_z_edges_vjp(line, eps, p, eab, ebb, lb);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lds_add(dst + i, J[0][i] * eab + J[1][i] * ebb + (i == 2 ? mb : 0.0));
+    for (int i = 0; i < 5; ++i) lds_add(dst + i, lb[i]);
   }
 }
 
@@ -165,11 +155,9 @@ __global__ void __launch_bounds__(256) flux_z_vjp_kernel(Geo g, const double* __
         zgp_field<double, DIR, false>(g, ff, ed, kZDl + k, a, t, sm, sl, X[kXDl + k], dum, dum, tok);
         zgp_field<double, DIR, false>(g, ff, ed, kZDr + k, a, t, sm, sl, X[kXDr + k], dum, dum, tok);
       }
-      // input cotangents Xb = J^T (Fb, dFb): one tangent per value column on the
-      // side it moves, the linear side maps for the 45 slopes
+      // input cotangents Xb = J^T (Fb, dFb) by the reverse sweep
       double Xb[kXN];
-      zflux_jt_value_pass<VAR_MU>(g, X, dt, Fb, dFb, Xb);
-      zflux_jt_slope_pass<VAR_MU>(g, X, dt, Fb, dFb, Xb);
+      zflux_vjp_pass<VAR_MU>(g, X, dt, Fb, dFb, Xb);
       // transpose of the tangential reconstruction, field by field
 #pragma unroll 1
       for (int k = 0; k < 5; ++k) {
@@ -228,14 +216,12 @@ __global__ void __launch_bounds__(256) flux_z_vjp_kernel(Geo g, const double* __
       const double slb = ffb[(kZDl + k) * TG::NFF + e] * ih;   // D_l = s_l / h
       const double srb = -ffb[(kZDr + k) * TG::NFF + e] * ih;  // D_r = -s_r / h
       double vb[6] = {0, 0, 0, 0, 0, 0};
-      double Jv[5], Js[5];
-      wzr_jac(v[k], eps, g.weno_p, Jv, Js);
-#pragma unroll
-      for (int i = 0; i < 5; ++i) vb[i] += Jv[i] * Qlb[k] + Js[i] * slb;
+      weno_z_right_vjp(v[k], eps, g.weno_p, Qlb[k], slb, vb);
       const double rv[5] = {v[k][5], v[k][4], v[k][3], v[k][2], v[k][1]};
-      wzr_jac(rv, eps, g.weno_p, Jv, Js);
+      double rvb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      weno_z_right_vjp(rv, eps, g.weno_p, Qrb[k], srb, rvb);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) vb[5 - i] += Jv[i] * Qrb[k] + Js[i] * srb;
+      for (int i = 0; i < 5; ++i) vb[5 - i] += rvb[i];
       // D_n = (v1 - 15 v2 + 15 v3 - v4) / (12 h)
       vb[1] += ih12 * Dnb;
       vb[2] -= 15.0 * ih12 * Dnb;

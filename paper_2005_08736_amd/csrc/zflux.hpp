@@ -375,8 +375,8 @@ struct ZAcc {
 
 // The moment rows of one side, without rho and the time coefficients: r[0..2]
 // = phi 1, a.u, A for p = 0 (density moments J), r[3..5] the same for p = 1 (flux
-// moments I).  With LIN the phi = 1 rows are zero.
-template <bool LIN = false, typename T>
+// moments I).
+template <typename T>
 __host__ __device__ __forceinline__ void zside_rows(const ZPrim<T>& s, const T (*D)[5], int half, T K, T (*r)[5]) {
   const T i2l = T(0.5) / s.lam;
   ZGauss<T> G;
@@ -419,10 +419,7 @@ __host__ __device__ __forceinline__ void zside_rows(const ZPrim<T>& s, const T (
   zrows<3, true>(M, eA, rA0, rA1);
   // phi = 1: C_0 = 1
   T r10[5], r11[5];
-  if (LIN) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) r10[k] = r11[k] = T(0);
-  } else {
+  {
     T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
     zrows<1, true>(M, e1, r10, r11);
   }
@@ -442,13 +439,11 @@ __host__ __device__ __forceinline__ void zside_rows(const ZPrim<T>& s, const T (
 // Adds rho (c0 <u^p psi> + c1 <u^p (a.u) psi> + c2 <u^p A psi>) for p = 1 (I)
 // and p = 0 (J) with the coefficient sets k1 (delta = dt) and kh (dt/2); the
 // time slope A solves <a.u + A> = 0 over the side's full-space Maxwellian.
-// With LIN the term of <psi> (the one part that does not scale with D) is left
-// out: the side's contribution is then linear in D.
-template <bool LIN = false, typename T>
+template <typename T>
 __host__ __device__ __forceinline__ void zside(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* k1,
                                                const T* kh, ZAcc<T>& acc, bool first) {
   T r[6][5];
-  zside_rows<LIN>(s, D, half, K, r);
+  zside_rows(s, D, half, K, r);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     T j1 = s.rho * (k1[0] * r[0][k] + k1[1] * r[1][k] + k1[2] * r[2][k]);
@@ -503,9 +498,7 @@ __host__ __device__ __forceinline__ void zflux_begin(const Geo& g, const T* dQ0,
   ztime(T(0.5) * dt, tau, c.eqh, c.inh);
 }
 
-// With LIN (acc linear in the slopes, zside<true>) the constant p_ref is not
-// taken out of the normal-momentum flux: F and dF stay linear in acc.
-template <bool LIN = false, typename T>
+template <typename T>
 __host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>& c, ZAcc<T>& acc, T dt, T* F, T* dF) {
   const T fix = T(g.pr_fix);
   acc.I1[4] = acc.I1[4] + fix * zheat(acc.I1, acc.J1, c.s0.U, c.s0.V, c.s0.W);
@@ -516,7 +509,7 @@ __host__ __device__ __forceinline__ void zflux_end(const Geo& g, const ZCoef<T>&
     F[k] = (T(4) * acc.Ih[k] - acc.I1[k]) * idt;
     dF[k] = T(4) * (acc.I1[k] - T(2) * acc.Ih[k]) * idt * idt;
   }
-  if (!LIN) F[1] = F[1] - T(g.p_ref);
+  F[1] = F[1] - T(g.p_ref);
 }
 
 // ---------------------------------------------------------------------------

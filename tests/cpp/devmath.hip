@@ -152,14 +152,25 @@ int dm_zflux_jt(const double* X, double dt, double gamma, double prandtl, double
   return 0;
 }
 
-// The same through the kernel's split: tangents for the values, the linear side
-// maps for the slopes
-int dm_zflux_jt_split(const double* X, double dt, double gamma, double prandtl, double mu, double T_ref,
-                      double mu_exp, double c_art, double rho_ref, double p_ref, const double* Fb, const double* dFb,
-                      double* Xb) {
+// The same by the kernel's hand-written reverse sweep
+int dm_zflux_vjp(const double* X, double dt, double gamma, double prandtl, double mu, double T_ref, double mu_exp,
+                 double c_art, double rho_ref, double p_ref, const double* Fb, const double* dFb, double* Xb) {
   Geo g = make_z(gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref);
   if (mu_exp != 0.0) zflux_jt_all<true>(g, X, dt, Fb, dFb, Xb);
   else zflux_jt_all<false>(g, X, dt, Fb, dFb, Xb);
+  return 0;
+}
+
+// The hand-written reverses of the WENO-Z edge pair and right-edge value/slope:
+// vb = J^T (cotangents)
+int dm_wze_vjp(const double* v, double eps, int p, double eab, double ebb, double* vb) {
+  for (int i = 0; i < 5; ++i) vb[i] = 0.0;
+  weno_z_edges_vjp(v, eps, p, eab, ebb, vb);
+  return 0;
+}
+int dm_wzr_vjp(const double* v, double eps, int p, double valb, double slopeb, double* vb) {
+  for (int i = 0; i < 5; ++i) vb[i] = 0.0;
+  weno_z_right_vjp(v, eps, p, valb, slopeb, vb);
   return 0;
 }
 

@@ -109,10 +109,10 @@ def zflux_jt(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb
     return Xb
 
 
-def zflux_jt_split(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb, dFb):
+def zflux_vjp(X, dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref, Fb, dFb):
     X, Fb, dFb = _a(X, 60), _a(Fb, 5), _a(dFb, 5)
     Xb = np.zeros(60)
-    lib().dm_zflux_jt_split(_p(X), *_zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref), _p(Fb),
+    lib().dm_zflux_vjp(_p(X), *_zargs(dt, gamma, prandtl, mu, T_ref, mu_exp, c_art, rho_ref, p_ref), _p(Fb),
                             _p(dFb), _p(Xb))
     return Xb
 
@@ -122,6 +122,21 @@ def wze_jac(v, eps, p):
     J = np.zeros((2, 5))
     lib().dm_wze_jac(_p(v), ctypes.c_double(eps), ctypes.c_int(p), _p(J))
     return J
+
+
+def wze_vjp(v, eps, p, eab, ebb):
+    v = _a(v, 5)
+    vb = np.zeros(5)
+    lib().dm_wze_vjp(_p(v), ctypes.c_double(eps), ctypes.c_int(p), ctypes.c_double(eab), ctypes.c_double(ebb), _p(vb))
+    return vb
+
+
+def wzr_vjp(v, eps, p, valb, slopeb):
+    v = _a(v, 5)
+    vb = np.zeros(5)
+    lib().dm_wzr_vjp(_p(v), ctypes.c_double(eps), ctypes.c_int(p), ctypes.c_double(valb), ctypes.c_double(slopeb),
+                     _p(vb))
+    return vb
 
 
 def wzr_jac(v, eps, p):
