@@ -56,9 +56,11 @@
 // Parity status: the moment algebra, slope solve, compatibility state, smooth and
 // full fluxes, reconstruction weights, stepping, conservation, uniform-flow
 // preservation, convergence order and early Taylor-Green decay are pinned by the
-// tests in tests/test_oracle_*.py.  The wall closure of the channel case is a
-// reading with no pin beyond conservation of the discrete momentum budget
-// ("parity unpinned" for the wall ghost values themselves).
+// tests in tests/test_oracle_*.py.  Of the wall closure of the channel case, the
+// isothermal part is pinned by the converging wall heat flux of a resting gas
+// with a linear temperature profile, and the whole closure by the discrete
+// momentum budget; the mirrored velocity at the wall rows is a reading with no
+// further pin ("parity unpinned" for the wall-row momentum flux).
 
 #include <algorithm>
 #include <cmath>

@@ -99,11 +99,19 @@ __device__ __forceinline__ ZEig<T> zeig_load(const T* p) {
   return e;
 }
 
+// The WENO-Z exponent: WP when it is fixed at compile time (the usual p = 2: 6%
+// faster, its kernels carry no branch on the exponent), else the run's parameter.
+template <int WP>
+__device__ __forceinline__ int zexp(const Geo& g) {
+  return WP > 0 ? WP : g.weno_p;
+}
+
 // Phase 1: face-field entries; the normal WENO-Z on characteristic variables.
-template <typename T, int DIR>
+template <typename T, int DIR, int WP>
 __device__ __forceinline__ void zcface_field(const Geo& g, const double* __restrict__ q, T* ff, int on, int o1,
                                              int o2) {
   using TG = ZTileGeom<DIR>;
+  const int wp = zexp<WP>(g);
   const T ih = T(g.inv_h[DIR]);
   const T ih12 = T(g.inv_h[DIR] * (1.0 / 12.0));
   const T eps = T(g.weno_eps);
@@ -142,9 +150,9 @@ __device__ __forceinline__ void zcface_field(const Geo& g, const double* __restr
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       T line[5] = {w[0][k], w[1][k], w[2][k], w[3][k], w[4][k]};
-      weno_z_right(line, eps, g.weno_p, wl[k], sl[k]);
+      weno_z_right(line, eps, wp, wl[k], sl[k]);
       T rline[5] = {w[5][k], w[4][k], w[3][k], w[2][k], w[1][k]};
-      weno_z_right(rline, eps, g.weno_p, wr[k], sr[k]);
+      weno_z_right(rline, eps, wp, wr[k], sr[k]);
     }
     T Ql[5], Qr[5], Dl[5], Dr[5];
     zright(ez, wl, Ql);
@@ -181,10 +189,11 @@ __device__ __forceinline__ int zc_line(int face, int r, int k) { return (face * 
 // characteristic variables, group g into lb + g * 3 * kZcLines.  Several groups
 // per pass fill the 256 threads better: one group is 320 jobs (two rounds, the
 // second a quarter full), two are 640 (three rounds) and three 960 (four).
-template <typename T, int DIR, int NG>
+template <typename T, int DIR, int NG, int WP>
 __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const T* eg, int f0a, int f0b, int f0c,
                                                T* lb) {
   using TG = ZTileGeom<DIR>;
+  const int wp = zexp<WP>(g);
   const T eps = T(g.weno_eps);
   for (int j = threadIdx.x; j < NG * 64 * 5; j += 256) {
     const int grp = j / (64 * 5), jj = j - grp * (64 * 5);
@@ -205,7 +214,7 @@ __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const 
     for (int k = 0; k < 5; ++k) {
       T line[5] = {w[0][k], w[1][k], w[2][k], w[3][k], w[4][k]};
       T ea, eb;
-      weno_z_edges(line, eps, g.weno_p, ea, eb);
+      weno_z_edges(line, eps, wp, ea, eb);
       const int li = zc_line(face, r, k);
       lg[3 * li] = w[2][k];
       lg[3 * li + 1] = ea;
@@ -223,10 +232,11 @@ __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const 
 // T1DER their t1-derivative rows) each lane evaluates every other one and the
 // pair swaps edges with a lane shuffle.  The arithmetic of each job is the same
 // on either lane, so the results do not depend on the split.
-template <typename T, int DIR, bool T1DER>
+template <typename T, int DIR, bool T1DER, int WP>
 __device__ __forceinline__ void zc_group_gp(const Geo& g, const T* lb, const ZEig<T>& ez, int face, T sm, T sl,
                                             T* val, T* d1, T* d2) {
   using TG = ZTileGeom<DIR>;
+  const int wp = zexp<WP>(g);
   const T eps = T(g.weno_eps);
   constexpr int J = T1DER ? 10 : 5;  // job j: component j % 5, t1-derivative rows if j >= 5
   const int mine = sl > T(0) ? 1 : 0;
@@ -245,7 +255,7 @@ __device__ __forceinline__ void zc_group_gp(const Geo& g, const T* lb, const ZEi
 #pragma unroll
     for (int r = 0; r < 5; ++r) rv[r] = row(jo, r);
     T ea, eb;
-    weno_z_edges(rv, eps, g.weno_p, ea, eb);
+    weno_z_edges(rv, eps, wp, ea, eb);
     const T pa = __shfl_xor(ea, 1), pb = __shfl_xor(eb, 1);
     // edges of j0 and j1 on both lanes
     const T ea0 = mine ? pa : ea, eb0 = mine ? pb : eb;
@@ -277,7 +287,7 @@ __device__ __forceinline__ void zc_group_gp(const Geo& g, const T* lb, const ZEi
   }
 }
 
-template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, int WP>
 __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                              const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   using TG = ZTileGeom<DIR>;
@@ -296,7 +306,7 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   const int o1 = ((tile / Nn) % nt1) * TG::B;
   const int o2 = (tile / (Nn * nt1)) * TG::B;
 
-  zcface_field<T, DIR>(g, q, ff, on, o1, o2);
+  zcface_field<T, DIR, WP>(g, q, ff, on, o1, o2);
   __syncthreads();
 
   const int tid = threadIdx.x;
@@ -323,20 +333,20 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   {
     T Ql[5], Qr[5], Q0[5], unused[5];
     if constexpr (NGS == 3) {
-      zc_group_lines<T, DIR, 3>(g, ff, eg, kZQl, kZQr, kZQ0, lb);
+      zc_group_lines<T, DIR, 3, WP>(g, ff, eg, kZQl, kZQr, kZQ0, lb);
       __syncthreads();
-      zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, Ql, unused, unused);
-      zc_group_gp<T, DIR, false>(g, lb + L, ez, face, sm, sl, Qr, unused, unused);
-      zc_group_gp<T, DIR, false>(g, lb + 2 * L, ez, face, sm, sl, Q0, unused, unused);
+      zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, Ql, unused, unused);
+      zc_group_gp<T, DIR, false, WP>(g, lb + L, ez, face, sm, sl, Qr, unused, unused);
+      zc_group_gp<T, DIR, false, WP>(g, lb + 2 * L, ez, face, sm, sl, Q0, unused, unused);
     } else {
       const int fs[3] = {kZQl, kZQr, kZQ0};
       T* out[3] = {Ql, Qr, Q0};
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         if (i > 0) __syncthreads();  // the previous group's lines have been read
-        zc_group_lines<T, DIR, 1>(g, ff, eg, fs[i], 0, 0, lb);
+        zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fs[i], 0, 0, lb);
         __syncthreads();
-        zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, out[i], unused, unused);
+        zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, out[i], unused, unused);
       }
     }
     zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
@@ -349,18 +359,18 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
     T D[3][5], unused[5];
     __syncthreads();  // the previous pass's lines have been read
     if constexpr (NGS == 3) {
-      zc_group_lines<T, DIR, 2>(g, ff, eg, fs, fd, 0, lb);
+      zc_group_lines<T, DIR, 2, WP>(g, ff, eg, fs, fd, 0, lb);
       __syncthreads();
-      zc_group_gp<T, DIR, true>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
-      zc_group_gp<T, DIR, false>(g, lb + L, ez, face, sm, sl, D[0], unused, unused);
+      zc_group_gp<T, DIR, true, WP>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
+      zc_group_gp<T, DIR, false, WP>(g, lb + L, ez, face, sm, sl, D[0], unused, unused);
     } else {
-      zc_group_lines<T, DIR, 1>(g, ff, eg, fs, 0, 0, lb);
+      zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fs, 0, 0, lb);
       __syncthreads();
-      zc_group_gp<T, DIR, true>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
+      zc_group_gp<T, DIR, true, WP>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
       __syncthreads();
-      zc_group_lines<T, DIR, 1>(g, ff, eg, fd, 0, 0, lb);
+      zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fd, 0, 0, lb);
       __syncthreads();
-      zc_group_gp<T, DIR, false>(g, lb, ez, face, sm, sl, D[0], unused, unused);
+      zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, D[0], unused, unused);
     }
     zfold_side(c, side, D, K, dt, o);
   }
@@ -393,12 +403,13 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
 #ifndef HGKS_ZCWAVES_F32
 #define HGKS_ZCWAVES_F32 3
 #endif
-template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+// WP: the WENO-Z exponent fixed at compile time (2), or 0 for the run's parameter
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, int WP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : HGKS_ZCWAVES_F32)))
 flux_zc_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
                const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   if (*stop) return;
-  flux_zc_body<T, DIR, STAGE2, VAR_MU>(g, q, fl, dtp, nt1, nt2, nper);
+  flux_zc_body<T, DIR, STAGE2, VAR_MU, WP>(g, q, fl, dtp, nt1, nt2, nper);
 }
 
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
@@ -408,8 +419,12 @@ static void launch_zc_dir(const Geo& g, const double* q, T* fl, const int* stop,
   const int nt2 = (g.n[TG::A2] + TG::B - 1) / TG::B;
   const int tiles = g.n[DIR] * nt1 * nt2;
   const int nper = (tiles + 7) / 8;
-  flux_zc_kernel<T, DIR, STAGE2, VAR_MU><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, dtp, nt1,
-                                                                                       nt2, nper);
+  if (g.weno_p == 2)
+    flux_zc_kernel<T, DIR, STAGE2, VAR_MU, 2><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, dtp,
+                                                                                             nt1, nt2, nper);
+  else
+    flux_zc_kernel<T, DIR, STAGE2, VAR_MU, 0><<<dim3(unsigned(8 * nper)), dim3(256), 0, st>>>(g, q, fl, stop, dtp,
+                                                                                             nt1, nt2, nper);
 }
 
 template <typename T, bool STAGE2, bool VAR_MU>

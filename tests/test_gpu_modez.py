@@ -44,6 +44,9 @@ CASES = {
     "iso16_ma07": lambda: (cases.isotropic_params(16, 0.7), cases.isotropic_state(16, 1, 0.7)),
     "ragged13x9x7": lambda: (lambda q: (ragged_z(q), q))(smooth_field(13, 9, 7, seed=21, amp=0.2)),
     "min6": lambda: (lambda q: (ragged_z(q), q))(smooth_field(6, 6, 6, seed=22, amp=0.2)),
+    # exponents other than the usual p = 2 run the kernels that read p at run time
+    "ragged13x9x7_p3": lambda: (lambda q: (ragged_z(q, weno_p=3), q))(smooth_field(13, 9, 7, seed=23, amp=0.2)),
+    "iso16_ma07_p1": lambda: (cases.isotropic_params(16, 0.7, weno_p=1), cases.isotropic_state(16, 2, 0.7)),
 }
 
 
@@ -57,6 +60,7 @@ def test_z_face_flux_matches_oracle(case, direction):
     F, dF = s.face_flux(direction, dt=dt)
     torch.cuda.synchronize()
     Fr, dFr = oracle.face_flux(p, q, direction, dt)
+    assert np.isfinite(Fr).all() and np.isfinite(dFr).all(), "the case must stay physical in the oracle"
     area = face_area(p, direction)
     Fr, dFr = Fr / area, dFr / area
     F, dF = F.cpu().numpy(), dF.cpu().numpy()
