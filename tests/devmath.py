@@ -1,6 +1,7 @@
 """Builds and loads tests/cpp/devmath.hip: the library's scalar device math
 compiled for the host, for CPU checks of the forward and adjoint formulas."""
 import ctypes
+import fcntl
 import os
 import subprocess
 
@@ -18,12 +19,17 @@ _D = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        newest = max(os.path.getmtime(p) for p in [SRC] + HDRS)
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
-            subprocess.run(["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
-                            "-o", LIB + ".tmp", SRC], check=True)
-            os.replace(LIB + ".tmp", LIB)
-        _lib = ctypes.CDLL(LIB)
+        # several test processes (pytest -n) may find the library stale at once:
+        # one builds it under the lock, the others wait and load the result
+        with open(LIB + ".lock", "w") as lock:
+            fcntl.flock(lock, fcntl.LOCK_EX)
+            newest = max(os.path.getmtime(p) for p in [SRC] + HDRS)
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
+                tmp = f"{LIB}.{os.getpid()}.tmp"
+                subprocess.run(["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                                "-o", tmp, SRC], check=True)
+                os.replace(tmp, LIB)
+            _lib = ctypes.CDLL(LIB)
     return _lib
 
 
