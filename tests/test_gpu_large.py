@@ -2,9 +2,11 @@
 device memory with the workspace) and 1024 x 1024 x 528 (5.5e8, about 221 GB).
 In both the ten-field face-flux arrays hold more than 2^32 values and the
 five-field state more than 2^31, so every 64-bit offset of the kernels is
-exercised.  The first box is below 2^29 cells, where the flux kernels read the
-state through 32-bit byte offsets (up to 3.5 GB into a field); the second is
-above it and takes their 64-bit addressing.  The oracle checks dt over the whole
+exercised.  The first box is below 2^29 cells, where the smooth-mode flux
+kernels read the state through 32-bit byte offsets (up to 3.5 GB into a field);
+the second is above it and takes their 64-bit addressing.  The first box is also
+stepped in mode Z and in its characteristic form, whose kernels address with
+64-bit offsets throughout.  The oracle checks dt over the whole
 box and Q^{n+1} at sampled cells (near the high corners too) from windows
 holding each cell's two-stage dependence.  The step adjoint runs on the first box
 too, with its own scratch array of face cotangents (10 N doubles) past 2^31
@@ -78,6 +80,46 @@ def test_large_box_64bit_offsets_sampled_step(nz):
         win = np.ascontiguousarray(q0[:, kk][:, :, jj][:, :, :, ii])
         pw = dict(p)
         pw.update(nx=13, ny=13, nz=13, lx=13 * h, ly=13 * h, lz=13 * h)
+        qw, _ = oracle.step(pw, win, 1, dt=dts[0])
+        got = q[:, c[2], c[1], c[0]].cpu().numpy()
+        ref = qw[:, 6, 6, 6]
+        announce(f"  cell {c}: max abs diff {np.abs(got - ref).max():.2e}")
+        assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(np.abs(ref), 1.0)), (c, got - ref)
+    s.close()
+    del s, q
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", [hgks.MODE_WENOZ, hgks.MODE_WENOZ_CHAR])
+def test_large_box_weno_z_modes_sampled_step(mode):
+    """One CFL step of the 1024 x 1024 x 416 box in mode Z and in its
+    characteristic form (WENO-Z weights, the full flux, mu(T)): dt against the
+    oracle over the whole box, Q^{n+1} at sampled cells (the high corners among
+    them) against the oracle on 13^3 windows."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test started without a ROCm device")
+    dev = torch.device("cuda:0")
+    nx, ny, nz = 1024, 1024, 416
+    p, h, q = large_field(nx, ny, nz, dev)
+    p.update(mode=mode, mu_exp=0.76, T_ref=71.4)
+    announce(f"large box {nx}x{ny}x{nz}, mode {mode}")
+    q0 = q.cpu().numpy()
+    s = hgks.Solver(p, q)
+    dts = s.step(1, return_dt=True)
+    torch.cuda.synchronize()
+    dt_ref = oracle.cfl_dt(p, q0)
+    announce(f"  dt {dts[0]:.15e}  oracle {dt_ref:.15e}")
+    assert abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.default_rng(7416 + mode)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))) for _ in range(3)]
+    pts += [(nx - 1, ny - 1, nz - 1), (nx - 7, ny - 1, nz - 2), (2, ny - 3, 0)]
+    pw = dict(p)
+    pw.update(nx=13, ny=13, nz=13, lx=13 * h, ly=13 * h, lz=13 * h)
+    for c in pts:
+        ii = np.arange(c[0] - 6, c[0] + 7) % nx
+        jj = np.arange(c[1] - 6, c[1] + 7) % ny
+        kk = np.arange(c[2] - 6, c[2] + 7) % nz
+        win = np.ascontiguousarray(q0[:, kk][:, :, jj][:, :, :, ii])
         qw, _ = oracle.step(pw, win, 1, dt=dts[0])
         got = q[:, c[2], c[1], c[0]].cpu().numpy()
         ref = qw[:, 6, 6, 6]
