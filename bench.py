@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--adjoint-reps", type=int, default=5)
     ap.add_argument("--other-steps", type=int, default=5,
                     help="timed steps of the isotropic (mode Z) and channel workloads (0: skip them)")
