@@ -72,10 +72,13 @@ __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz,
     y0 = (r % nty) * TG::BY;
     z0 = (r / nty) * TG::BZ;
   } else {
-    z0 = (tile % ntz) * TG::BZ;
-    const int r = tile / ntz;
-    x0 = (r % ntx) * TG::BX;
-    y0 = (r / ntx) * TG::BY;
+    // z-faces: x first, then z, then y: the tiles resident on one XCD cover a
+    // few z-planes of a slab of y-rows whole in x, so that both the x-halo and
+    // the shared stencil planes along z stay in its L2
+    x0 = (tile % ntx) * TG::BX;
+    const int r = tile / ntx;
+    z0 = (r % ntz) * TG::BZ;
+    y0 = (r / ntz) * TG::BY;
   }
 }
 
