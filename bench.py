@@ -58,8 +58,8 @@ FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # factors make the same counters read the known 671 MB in / 671 MB out of the
 # library's copy kernel.  Valid only for the kernel sources with this digest
 # (profiles/flux_fused_tgv256_kernels.md).
-FLUX_STAGE1_HBM_BYTES_PER_FACE = 175.7
-FLUX_COUNTERS_SOURCE_DIGEST = "a8b024f9195273bb"
+FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.7
+FLUX_COUNTERS_SOURCE_DIGEST = "33748dd32de771f1"
 
 
 def kernel_source_digest():
