@@ -17,9 +17,8 @@
 //      (60 values), from which the full gas distribution of Eq. (flux), integrated
 //      over dt and dt/2, gives F^n and dF^n/dt (Eq. (expansion-1)).  The four
 //      Gauss points of a face sit in adjacent lanes and are summed with shuffles.
-// Tiles are numbered with the normal axis fastest (neighbouring tiles along the
-// normal share five of their six stencil planes) and dealt to the XCDs in
-// contiguous ranges.
+// Tiles are dealt to the XCDs in contiguous ranges, in the order of
+// zflux_tile_origin (ztile.hpp).
 #include "internal.hpp"
 #include "ztile.hpp"
 
@@ -34,9 +33,8 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   const int tile = tile_of_block(nper);
   const int Nn = g.n[DIR];
   if (tile >= Nn * nt1 * nt2) return;  // whole workgroup leaves together
-  const int on = tile % Nn;
-  const int o1 = ((tile / Nn) % nt1) * TG::B;
-  const int o2 = (tile / (Nn * nt1)) * TG::B;
+  int on, o1, o2;
+  zflux_tile_origin<DIR>(tile, Nn, nt1, nt2, on, o1, o2);
 
   zface_field<T, DIR>(g, q, ff, on, o1, o2);
   __syncthreads();

@@ -302,9 +302,8 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   const int tile = tile_of_block(nper);
   const int Nn = g.n[DIR];
   if (tile >= Nn * nt1 * nt2) return;  // whole workgroup leaves together
-  const int on = tile % Nn;
-  const int o1 = ((tile / Nn) % nt1) * TG::B;
-  const int o2 = (tile / (Nn * nt1)) * TG::B;
+  int on, o1, o2;
+  zflux_tile_origin<DIR>(tile, Nn, nt1, nt2, on, o1, o2);
 
   zcface_field<T, DIR, WP>(g, q, ff, on, o1, o2);
   __syncthreads();

@@ -25,6 +25,28 @@ struct ZTileGeom {
   static constexpr int NF = 30;                                 // fields per entry
 };
 
+// Tile order.  x-faces: the normal axis fastest (neighbouring tiles along the
+// normal share five of their six stencil planes).  y- and z-faces: the x tiles
+// first, then the normal, then the remaining axis, so that the tiles resident on
+// one XCD cover a few planes of a slab of rows whole in x.
+template <int DIR>
+__device__ __forceinline__ void zflux_tile_origin(int tile, int Nn, int nt1, int nt2, int& on, int& o1, int& o2) {
+  using TG = ZTileGeom<DIR>;
+  if (DIR == 0) {
+    on = tile % Nn;
+    o1 = ((tile / Nn) % nt1) * TG::B;
+    o2 = (tile / (Nn * nt1)) * TG::B;
+  } else if (DIR == 1) {  // t1 = z, t2 = x
+    o2 = (tile % nt2) * TG::B;
+    on = (tile / nt2) % Nn;
+    o1 = (tile / (nt2 * Nn)) * TG::B;
+  } else {  // t1 = x, t2 = y
+    o1 = (tile % nt1) * TG::B;
+    on = (tile / nt1) % Nn;
+    o2 = (tile / (nt1 * Nn)) * TG::B;
+  }
+}
+
 // field numbering in LDS
 constexpr int kZQ0 = 0, kZDn = 5, kZQl = 10, kZQr = 15, kZDl = 20, kZDr = 25;
 
