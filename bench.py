@@ -59,7 +59,7 @@ FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # library's copy kernel.  Valid only for the kernel sources with this digest
 # (profiles/flux_fused_tgv256_kernels.md).
 FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.7
-FLUX_COUNTERS_SOURCE_DIGEST = "33748dd32de771f1"
+FLUX_COUNTERS_SOURCE_DIGEST = "e2d606e73ba8b26a"
 
 
 def kernel_source_digest():

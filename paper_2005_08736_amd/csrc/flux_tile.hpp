@@ -53,10 +53,11 @@ __host__ __device__ __forceinline__ int gcomp_local(int local) {
 // XCD-aware tile order: block b runs on XCD b % 8 and takes tile (b % 8) * nper + b / 8
 __device__ __forceinline__ int tile_of_block(int nper) { return int(blockIdx.x % 8u) * nper + int(blockIdx.x / 8u); }
 
-// Origin (first face) of a tile.  x- and z-face tiles are numbered with the
-// normal axis fastest: the next tile along the normal shares five of the six
-// stencil planes, and the blocks resident on one XCD at a time (a contiguous
-// range of tiles) cover a short column of planes that stays in its L2.
+// Origin (first face) of a tile.  x-face tiles are numbered with the normal
+// axis fastest: the next tile along the normal shares five of the six stencil
+// planes, and the blocks resident on one XCD at a time (a contiguous range of
+// tiles) cover a short column of planes that stays in its L2.  y- and z-face
+// tiles are numbered x first (see each branch).
 template <int DIR, class TG = TileGeom<DIR>>
 __device__ __forceinline__ void tile_origin(int tile, int ntx, int nty, int ntz, int& x0, int& y0, int& z0) {
   if (DIR == 0) {
