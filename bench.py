@@ -426,9 +426,12 @@ def main():
         "closed_form_flop_per_face": FLUX_STAGE1_CLOSED_FORM_FLOPS_PER_FACE,
         "frac_executed": executed / PEAK_FP64_VECTOR_TFLOPS if executed is not None else None,
         "executed_flop_per_face": FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE if counters_current else None,
+        # the same launch against the HBM roof: measured traffic over the live launch time
+        "hbm_achieved_gbs": traffic / avg_flux_s / 1e9 if traffic is not None else None,
+        "hbm_frac": traffic / avg_flux_s / 1e9 / PEAK_HBM_GBS if traffic is not None else None,
         "note": "frac prices each face at the scheme's operation count; frac_closed_form at the closed-form "
                 "smooth flux this kernel evaluates; frac_executed at the FP64 operations the kernel issues "
-                "(rocprofv3 counters)",
+                "(rocprofv3 counters); hbm_frac is the measured traffic rate against 8 TB/s",
     }
     d = r64["solver"].diagnostics()
     log(f"[bench] after {args.warmup + args.steps} steps: E_k={d['E_k']:.8f} min_p={d['min_p']:.6f}")
