@@ -471,7 +471,9 @@ __host__ __device__ __forceinline__ void zside_rows_rev(const ZPrim<double>& s, 
 __host__ __device__ __forceinline__ double ztime_rev(double delta, double tau, const double* eqb, const double* inb) {
   const double e = exp(-delta / tau);
   const double om = 1.0 - e;
-  const double et = e * delta / (tau * tau);  // d e / d tau
+  // d e / d tau; where e has underflowed (tau = 0 in an inviscid run without the
+  // artificial term, or delta >> tau) its limit 0 is taken instead of 0 / 0
+  const double et = e > 0.0 ? e * delta / (tau * tau) : 0.0;
   double r = 0.0;
   r += eqb[0] * (-om + tau * et);
   r += eqb[1] * (4.0 * tau * om - 2.0 * tau * tau * et - delta * (1.0 + e) - tau * delta * et);

@@ -2,6 +2,7 @@
 compiled for the host, for CPU checks of the forward and adjoint formulas."""
 import ctypes
 import fcntl
+import glob
 import os
 import subprocess
 
@@ -10,8 +11,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cpp", "devmath.hip")
 LIB = os.path.join(HERE, "cpp", "libdevmath.so")
-HDRS = [os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", n)
-        for n in ("device_common.hpp", "adjoint_common.hpp", "zflux.hpp", "tangent.hpp", "zadjoint_common.hpp")]
+# every library header: the device math includes several of them, directly or not
+HDRS = sorted(glob.glob(os.path.join(HERE, "..", "paper_2005_08736_amd", "csrc", "*.hpp")))
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 

@@ -194,6 +194,34 @@ def _z_inputs(p_level, rho_ref, p_ref):
     return np.concatenate([Q0 - ref, Ql - ref, Qr - ref, slopes])
 
 
+def test_zflux_reverse_without_viscosity_is_finite_and_matches_central_differences():
+    """With mu = 0 and no artificial term the collision time is exactly zero and
+    exp(-dt/tau) underflows to 0; the reverse sweep takes the limit 0 of its tau
+    derivative there (tau is constant, so that term carries no cotangent), and
+    J^T (Fb, dFb) still matches central differences of the forward flux."""
+    rho_ref, p_ref = 1.0, 1.0
+    args_base = (GAMMA, 0.72, 0.0, 1.0, 0.0, 0.0, rho_ref, p_ref)
+    for i in range(4):
+        X = _z_inputs(1.0, rho_ref, p_ref)
+        dt = [1e-3, 1e-2][i % 2]
+        args = (dt,) + args_base
+        Fb, dFb = rng.normal(size=5), rng.normal(size=5)
+        Xs = devmath.zflux_vjp(X, *args, Fb, dFb)
+        assert np.all(np.isfinite(Xs))
+
+        def f(x):
+            F, dF = devmath.zgp_flux(x, *args)
+            return np.concatenate([F, dF])
+
+        wb = np.concatenate([Fb, dFb])
+        for _ in range(3):
+            v = rng.normal(size=60) * np.abs(X).clip(1e-2)
+            fd = _fd_check(f, X, v, wb, 1e-5)
+            got = float(Xs @ v)
+            sc = sum(abs(_fd_check(f, X, v * (np.arange(60) == j), wb, 1e-5)) for j in range(0, 60, 7)) + abs(fd)
+            assert abs(got - fd) <= 1e-6 * sc, (i, got, fd, sc)
+
+
 @pytest.mark.parametrize("p_level,mu_exp", [(1.0, 0.0), (2.86, 0.76), (71.4, 0.0)])
 def test_zflux_jacobian_transpose_matches_central_differences(p_level, mu_exp):
     """J^T (Fb, dFb) of the mode-Z Gauss-point flux (full distribution, time

@@ -105,6 +105,34 @@ def test_z_step_vjp_symmetric_field_ties():
     assert abs(lhs - rhs) <= 1e-9 * scale, (lhs, rhs, scale)
 
 
+def test_z_step_vjp_without_viscosity_against_oracle_differences():
+    """mu = 0 and no artificial term: the collision time is exactly zero and
+    exp(-dt/tau) underflows.  The adjoint stays finite and <J^T lambda, v> matches
+    central differences of the oracle's step along v.  (The oracle's dual-number
+    JVP cannot serve here: its derivative of -dt/tau is 0/0 at tau = 0.)"""
+    announce("mode Z step vjp, mu = 0 and c_art = 0, ragged 12x10x8")
+    q = smooth_field(12, 10, 8, seed=33)
+    p = cases.params(nx=12, ny=10, nz=8, lx=2 * math.pi, ly=1.7 * math.pi, lz=1.3 * math.pi, mu_ref=0.0, c_art=0.0,
+                     prandtl=0.7, mode=1)
+    dt = 0.5 * oracle.cfl_dt(p, q)
+    rng = np.random.default_rng(11)
+    qd = to_dev(q)
+    st = ag.Stepper(p, qd)
+    v = rng.normal(size=q.shape) * np.array([1e-2, 1e-2, 1e-2, 1e-2, 1e-1])[:, None, None, None]
+    lam = rng.normal(size=q.shape)
+    vjp = st.vjp(qd, dt, to_dev(lam)).cpu().numpy()
+    assert np.all(np.isfinite(vjp))
+    rhs = float(np.sum(vjp * v))
+    h = 1e-5
+    qp, _ = oracle.step(p, q + h * v, 1, dt=dt)
+    qm, _ = oracle.step(p, q - h * v, 1, dt=dt)
+    cd = (qp - qm) / (2 * h)
+    lhs = float(np.sum(lam * cd))
+    scale = math.sqrt(float(np.sum(lam ** 2)) * float(np.sum(cd ** 2)))
+    announce(f"  <lam, CD> = {lhs:.15e}  <J^T lam, v> = {rhs:.15e}  rel to scale {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-7 * scale, (lhs, rhs, scale)
+
+
 def test_z_step_vjp_unsupported_fp32_form():
     p, q = tgv_z(16), cases.tgv_state(16)
     p = dict(p)
