@@ -47,6 +47,9 @@ CASES = {
     # exponents other than the usual p = 2 run the kernels that read p at run time
     "ragged13x9x7_p3": lambda: (lambda q: (ragged_z(q, weno_p=3), q))(smooth_field(13, 9, 7, seed=23, amp=0.2)),
     "iso16_ma07_p1": lambda: (cases.isotropic_params(16, 0.7, weno_p=1), cases.isotropic_state(16, 2, 0.7)),
+    # no viscosity and no artificial term: the collision time is exactly zero
+    "ragged13x9x7_inviscid": lambda: (lambda q: (ragged_z(q, mu_ref=0.0, c_art=0.0), q))(
+        smooth_field(13, 9, 7, seed=24, amp=0.2)),
 }
 
 

@@ -52,6 +52,9 @@ CASES = {
     "min6": lambda: (lambda q: (ragged_c(q), q))(smooth_field(6, 6, 6, seed=42, amp=0.2)),
     # an exponent other than the usual p = 2 runs the kernels that read p at run time
     "ragged13x9x7_p3": lambda: (lambda q: (ragged_c(q, weno_p=3), q))(smooth_field(13, 9, 7, seed=43, amp=0.2)),
+    # no viscosity and no artificial term: the collision time is exactly zero
+    "ragged13x9x7_inviscid": lambda: (lambda q: (ragged_c(q, mu_ref=0.0, c_art=0.0), q))(
+        smooth_field(13, 9, 7, seed=44, amp=0.2)),
 }
 
 
