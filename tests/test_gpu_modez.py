@@ -50,6 +50,9 @@ CASES = {
     # no viscosity and no artificial term: the collision time is exactly zero
     "ragged13x9x7_inviscid": lambda: (lambda q: (ragged_z(q, mu_ref=0.0, c_art=0.0), q))(
         smooth_field(13, 9, 7, seed=24, amp=0.2)),
+    # a monatomic gas: no internal degrees of freedom (K = 0)
+    "ragged13x9x7_monatomic": lambda: (lambda q: (ragged_z(q, gamma=5.0 / 3.0), q))(
+        smooth_field(13, 9, 7, seed=25, amp=0.2, gamma=5.0 / 3.0)),
 }
 
 

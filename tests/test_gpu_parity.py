@@ -74,6 +74,9 @@ CASES = {
     "tgv32": lambda: (cases.tgv_params(32), cases.tgv_state(32)),
     "ragged13x9x7": lambda: (lambda q: (ragged_params(q), q))(smooth_field(13, 9, 7, seed=11)),
     "min6": lambda: (lambda q: (ragged_params(q), q))(smooth_field(6, 6, 6, seed=12)),
+    # a monatomic gas: no internal degrees of freedom (K = 0)
+    "ragged13x9x7_monatomic": lambda: (lambda q: (ragged_params(q, gamma=5.0 / 3.0), q))(
+        smooth_field(13, 9, 7, seed=13, gamma=5.0 / 3.0)),
 }
 
 
