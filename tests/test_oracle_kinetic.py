@@ -144,14 +144,19 @@ def ns_flux(Q, dQ, mu, prandtl, g=GAMMA):
 
 
 @pytest.mark.parametrize("prandtl", [1.0, 0.72])
-def test_smooth_flux_is_navier_stokes(oracle_mod, prandtl):
+@pytest.mark.parametrize("gamma", [GAMMA, 5.0 / 3.0, 1.3])
+def test_smooth_flux_is_navier_stokes(oracle_mod, prandtl, gamma):
+    """For every gamma, K = (5 - 3 gamma)/(gamma - 1) internal degrees of freedom:
+    the monatomic gas (K = 0) has no bulk viscosity, K = 2 (gamma = 1.4) gives
+    4/15 mu, K = 11/3 (gamma = 1.3) 11/30 mu."""
     for _ in range(5):
-        Q = random_state()
+        r, U, pr = 0.5 + rng.random(), rng.normal(size=3), 0.5 + rng.random()
+        Q = cons(r, *U, pr, g=gamma)
         dQ = rng.normal(size=(3, 5)) * 0.3
         tau = 0.02 * rng.random()
-        F0, _ = oracle_mod.gp_flux_smooth(Q, dQ.ravel(), tau, GAMMA, prandtl)
-        _, _, p = prim(Q)
-        ref = ns_flux(Q, dQ, tau * p, prandtl)
+        F0, _ = oracle_mod.gp_flux_smooth(Q, dQ.ravel(), tau, gamma, prandtl)
+        _, _, p = prim(Q, gamma)
+        ref = ns_flux(Q, dQ, tau * p, prandtl, gamma)
         assert np.allclose(F0, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
 
 
