@@ -176,13 +176,15 @@ def test_prandtl_fix_on_time_derivative(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
-def test_full_flux_reduces_to_smooth_for_continuous_data(oracle_mod):
+@pytest.mark.parametrize("gamma", [GAMMA, 5.0 / 3.0, 1.3])
+def test_full_flux_reduces_to_smooth_for_continuous_data(oracle_mod, gamma):
     for _ in range(4):
-        Q = random_state()
+        r, U, pr = 0.5 + rng.random(), rng.normal(size=3), 0.5 + rng.random()
+        Q = cons(r, *U, pr, g=gamma)
         dQ = rng.normal(size=(3, 5)) * 0.3
         tau, dt = 0.003 + 0.01 * rng.random(), 0.01 + 0.02 * rng.random()
-        F, dF = oracle_mod.gp_flux_full(Q, dQ.ravel(), Q, dQ.ravel(), Q, dQ.ravel(), tau, dt, GAMMA, 0.72)
-        F0, F1 = oracle_mod.gp_flux_smooth(Q, dQ.ravel(), tau, GAMMA, 0.72)
+        F, dF = oracle_mod.gp_flux_full(Q, dQ.ravel(), Q, dQ.ravel(), Q, dQ.ravel(), tau, dt, gamma, 0.72)
+        F0, F1 = oracle_mod.gp_flux_smooth(Q, dQ.ravel(), tau, gamma, 0.72)
         assert np.allclose(F, F0, rtol=1e-12, atol=1e-12 * np.abs(F0).max())
         assert np.allclose(dF, F1, rtol=1e-9, atol=1e-9 * np.abs(F1).max())
 
