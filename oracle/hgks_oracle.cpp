@@ -58,9 +58,11 @@
 // preservation, convergence order and early Taylor-Green decay are pinned by the
 // tests in tests/test_oracle_*.py.  Of the wall closure of the channel case, the
 // isothermal part is pinned by the converging wall heat flux of a resting gas
-// with a linear temperature profile, and the whole closure by the discrete
-// momentum budget; the mirrored velocity at the wall rows is a reading with no
-// further pin ("parity unpinned" for the wall-row momentum flux).
+// with a linear temperature profile, the mirrored velocity by the exact wall
+// shear stress of a linear profile that vanishes at the wall, and the whole
+// closure by the discrete momentum budget.  On curved profiles the mirrored
+// velocity's wall-row error does not converge; that remains a reading ("parity
+// unpinned" for the wall-row momentum flux of such profiles).
 
 #include <algorithm>
 #include <cmath>

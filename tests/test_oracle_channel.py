@@ -1,6 +1,7 @@
 """Pins of the oracle's channel set-up (Sec. 3.3): isothermal no-slip walls in
 y by mirror ghosts, the tanh wall-normal mesh and the constant body force."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_2005_08736_amd import cases
@@ -121,6 +122,39 @@ def test_isothermal_wall_carries_the_fourier_heat_flux():
         assert np.abs(top[2] - p0).max() <= 1e-3 * p0
     assert errs[-1] < 1e-3, errs
     assert all(errs[i] / errs[i + 1] > 1.5 for i in range(3)), errs
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_no_slip_wall_carries_the_exact_shear_stress_of_a_linear_profile(wall):
+    """Uniform density and temperature (T = T_wall) and a streamwise velocity
+    that vanishes linearly at one wall, U = alpha (y + 1) at the bottom or
+    alpha (1 - y) at the top, on a uniform mesh.  The mirrored ghost velocity
+    (U_g = -U of the mirror cell) continues that line exactly through the wall,
+    every reconstruction is exact on it, and the wall face must carry the
+    Navier-Stokes shear stress: x-momentum flux -mu dU/dy (= -mu alpha at the
+    bottom, +mu alpha at the top) to rounding, no mass, z-momentum or energy
+    flux, and no time derivative (the state's Euler time derivative is zero).
+    A slip (even) mirror, a ghost mirrored about the wrong row or a wrong
+    viscous stress fails it."""
+    gamma, Pr, mu, Tw, alpha = 1.4, 0.72, 0.02, 1.0, 0.3
+    for ny in (8, 16, 32):
+        p = cases.params(nx=6, ny=ny, nz=6, lx=1.0, ly=2.0, lz=1.0, bc_y=1, stretch_b=0.0, gamma=gamma,
+                         prandtl=Pr, mu_ref=mu, T_ref=Tw, T_wall=Tw, body_force_x=0.0)
+        yc = -1.0 + (np.arange(ny) + 0.5) * (2.0 / ny)
+        U = alpha * (yc + 1.0) if wall == 0 else alpha * (1.0 - yc)
+        q = np.zeros((5, 6, ny, 6))
+        q[0] = 1.0
+        q[1] = U[None, :, None]
+        q[4] = Tw / (gamma - 1.0) + 0.5 * (U ** 2)[None, :, None]
+        F, dF = oracle.wall_flux(p, q)
+        area = p["lx"] / 6 * p["lz"] / 6
+        f, df = F[wall] / area, dF[wall] / area
+        tau_w = -mu * alpha if wall == 0 else mu * alpha
+        assert np.abs(f[1] - tau_w).max() <= 1e-14 * mu * alpha, (ny, np.abs(f[1] - tau_w).max())
+        assert np.abs(f[0]).max() <= 1e-15 and np.abs(f[3]).max() <= 1e-15
+        # the energy flux is formed from O(1) temperatures differenced across the wall
+        assert np.abs(f[4]).max() <= 1e-15
+        assert np.abs(df).max() <= 1e-13
 
 
 def test_channel_x_momentum_budget_closes():
