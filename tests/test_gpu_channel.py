@@ -290,6 +290,36 @@ def test_channel_wall_flux_matches_oracle(case):
     assert torch.equal(torch.from_numpy(F[1]), Fy[:, :, -1, :].cpu())
 
 
+@pytest.mark.parametrize("precision", [hgks.PREC_F64, hgks.PREC_F32FLUX])
+def test_channel_wall_carries_the_exact_shear_of_a_linear_profile(precision):
+    """The oracle pin of the velocity mirror, on the device: uniform density and
+    T = T_wall, U vanishing linearly at the bottom wall and, in a second field, at
+    the top one, on a uniform mesh of 16 x 24 x 8.  The wall face must carry the
+    x-momentum flux -mu dU/dy exactly (FP64 to 1e-14 of it; the FP32-flux form to
+    its own rounding, 1e-6), with no mass or z-momentum flux."""
+    gamma, Pr, mu, Tw, alpha = 1.4, 0.72, 0.02, 1.0, 0.3
+    nx, ny, nz = 16, 24, 8
+    p = dict(cases.params(nx=nx, ny=ny, nz=nz, lx=1.0, ly=2.0, lz=0.5, bc_y=1, stretch_b=0.0, gamma=gamma,
+                          prandtl=Pr, mu_ref=mu, T_ref=Tw, T_wall=Tw, body_force_x=0.0), precision=precision)
+    yc = -1.0 + (np.arange(ny) + 0.5) * (2.0 / ny)
+    tol = 1e-14 if precision == hgks.PREC_F64 else 1e-6
+    for wall in (0, 1):
+        announce(f"channel wall shear, linear profile at wall {wall}, precision {precision}")
+        U = alpha * (yc + 1.0) if wall == 0 else alpha * (1.0 - yc)
+        q = np.zeros((5, nz, ny, nx))
+        q[0] = 1.0
+        q[1] = U[None, :, None]
+        q[4] = Tw / (gamma - 1.0) + 0.5 * (U ** 2)[None, :, None]
+        s = hgks.Solver(p, to_dev(q))
+        F, _ = s.wall_flux()
+        torch.cuda.synchronize()
+        f = F.cpu().numpy()[wall]  # face averages
+        tau_w = -mu * alpha if wall == 0 else mu * alpha
+        assert np.abs(f[1] - tau_w).max() <= tol * mu * alpha, (wall, np.abs(f[1] - tau_w).max())
+        assert np.abs(f[0]).max() <= tol * mu * alpha and np.abs(f[3]).max() <= tol * mu * alpha
+        s.close()
+
+
 def test_channel_wall_flux_needs_walls():
     p = cases.tgv_params(8)
     s = hgks.Solver(p, to_dev(cases.tgv_state(8)))
