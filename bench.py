@@ -60,14 +60,42 @@ FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # (profiles/flux_fused_tgv256_kernels.md).
 FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.7
 FLUX_COUNTERS_SOURCE_DIGEST = "e2d606e73ba8b26a"
+# The same counters for the stage-1 FP64 flux of mode Z and of its characteristic
+# form at 256^3 (mean of the three directions; profiles/flux_z_isotropic256_kernels.md
+# and profiles/flux_zc_shocklet256_kernels.md), per mode: executed FP64 operations
+# per face (FMA = 2), HBM bytes per face, and the digest of the sources they hold for.
+FLUX_Z_COUNTERS = {
+    1: {"executed_flop_per_face": (40007 + 40009 + 40008) / 3, "hbm_bytes_per_face": (2404.0 + 2609.2 + 2634.1) / 3,
+        "sources": ("flux_z.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "9c13958fab1fc97b"},
+    2: {"executed_flop_per_face": (75870 + 75878 + 75872) / 3, "hbm_bytes_per_face": (403.7 + 494.3 + 487.3) / 3,
+        "sources": ("flux_zc.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "9f49c50ec4aa5f9d"},
+}
 
 
-def kernel_source_digest():
+def kernel_source_digest(names=("flux_fused.hip", "flux_tile.hpp", "device_common.hpp")):
     h = hashlib.sha256()
-    for name in ("flux_fused.hip", "flux_tile.hpp", "device_common.hpp"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2005_08736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def zflux_roofline(mode: int, faces: int, avg_launch_s: float) -> dict:
+    """Roofline of the stage-1 FP64 flux launch of mode Z or its characteristic
+    form: priced at the scheme's count per face (frac), and, while the sources are
+    those the counters were taken on, at the FP64 operations the kernel issues
+    (frac_executed) with its measured HBM traffic."""
+    ach = FLUX_Z_FLOPS_PER_FACE * faces / avg_launch_s / 1e12
+    out = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+           "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "flop_per_face": FLUX_Z_FLOPS_PER_FACE,
+           "frac_executed": None, "executed_flop_per_face": None, "traffic": None, "hbm_frac": None}
+    c = FLUX_Z_COUNTERS.get(mode)
+    if c is not None and kernel_source_digest(c["sources"]) == c["digest"]:
+        ex = c["executed_flop_per_face"] * faces / avg_launch_s / 1e12
+        traffic = c["hbm_bytes_per_face"] * faces
+        out.update(frac_executed=ex / PEAK_FP64_VECTOR_TFLOPS, executed_flop_per_face=c["executed_flop_per_face"],
+                   traffic=traffic, hbm_frac=traffic / avg_launch_s / 1e9 / PEAK_HBM_GBS)
+    return out
 
 
 def log(*a):
@@ -237,12 +265,9 @@ def shocklet_run(args, torch, np, cases, hgks, dev, mode, n=256, ma_t=1.0, seed=
     s.profile(False)
     s.close()
     ms1, c1 = prof["flux_stage1"]
-    ach = FLUX_Z_FLOPS_PER_FACE * N / (ms1 / max(c1, 1) / 1e3) / 1e12
     out["fp64"] = {"value": N * steps / el / 1e6, "unit": UNIT, "ms_per_step": el / steps * 1e3,
                    "dt_first": dts[0], "dt_last": dts[-1], "flux_stage1_avg_launch_ms": ms1 / max(c1, 1),
-                   "flux_roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                                     "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
-                                     "flop_per_face": FLUX_Z_FLOPS_PER_FACE}}
+                   "flux_roofline": zflux_roofline(p["mode"], N, ms1 / max(c1, 1) / 1e3)}
     log(f"[bench] shocklet FP64: {el / steps * 1e3:.2f} ms/step, {out['fp64']['value']:.1f} Mcell-updates/s")
     b = torch.from_numpy(q0).to(dev)
     s32 = hgks.Solver(dict(p, precision=hgks.PREC_F32FLUX), b)
@@ -294,10 +319,7 @@ def other_workloads(args, torch, np, cases, hgks, dev):
         r = {"value": n * steps / el / 1e6, "unit": UNIT, "ms_per_step": el / steps * 1e3, "steps": steps,
              "cells": n, "dt": dts[0], "flux_stage1_avg_launch_ms": ms1 / max(c1, 1)}
         if p["mode"] != hgks.MODE_SMOOTH and p.get("precision", hgks.PREC_F64) == hgks.PREC_F64:
-            ach = FLUX_Z_FLOPS_PER_FACE * n / (ms1 / max(c1, 1) / 1e3) / 1e12
-            r["flux_roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                                  "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
-                                  "flop_per_face": FLUX_Z_FLOPS_PER_FACE}
+            r["flux_roofline"] = zflux_roofline(p["mode"], n, ms1 / max(c1, 1) / 1e3)
         log(f"[bench] {name}: {r['ms_per_step']:.2f} ms/step, {r['value']:.1f} Mcell-updates/s")
         s.close()
         return r, q
