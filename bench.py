@@ -48,7 +48,7 @@ FLUX_STAGE1_CLOSED_FORM_FLOPS_PER_FACE = 639 + 2320
 # (halo recomputation included; mean of the three directions, FMA = 2), from
 # rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 for the sources with the digest below.
 # Reported as `frac_executed`: the share of the FMA peak the kernel issues.
-FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE = (2505 + 2417 + 2417) / 3
+FLUX_STAGE1_EXECUTED_FLOPS_PER_FACE = (2453 + 2371 + 2371) / 3
 # Mode Z (WENO-Z reconstruction, full flux integrated over the step): the
 # scheme's count per cell-update, about 1e5 FP64 operations over the two stages
 # and three directions, i.e. 1e5 / 6 per face and stage.
@@ -58,17 +58,17 @@ FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # factors make the same counters read the known 671 MB in / 671 MB out of the
 # library's copy kernel.  Valid only for the kernel sources with this digest
 # (profiles/flux_fused_tgv256_kernels.md).
-FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.7
-FLUX_COUNTERS_SOURCE_DIGEST = "e2d606e73ba8b26a"
+FLUX_STAGE1_HBM_BYTES_PER_FACE = 156.1
+FLUX_COUNTERS_SOURCE_DIGEST = "5cb3bf1de8040b20"
 # The same counters for the stage-1 FP64 flux of mode Z and of its characteristic
 # form at 256^3 (mean of the three directions; profiles/flux_z_isotropic256_kernels.md
 # and profiles/flux_zc_shocklet256_kernels.md), per mode: executed FP64 operations
 # per face (FMA = 2), HBM bytes per face, and the digest of the sources they hold for.
 FLUX_Z_COUNTERS = {
-    1: {"executed_flop_per_face": (40007 + 40009 + 40008) / 3, "hbm_bytes_per_face": (2404.0 + 2609.2 + 2634.1) / 3,
-        "sources": ("flux_z.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "9c13958fab1fc97b"},
-    2: {"executed_flop_per_face": (75870 + 75878 + 75872) / 3, "hbm_bytes_per_face": (403.7 + 494.3 + 487.3) / 3,
-        "sources": ("flux_zc.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "9f49c50ec4aa5f9d"},
+    1: {"executed_flop_per_face": (39929 + 39931 + 39930) / 3, "hbm_bytes_per_face": (2403.1 + 2607.6 + 2630.4) / 3,
+        "sources": ("flux_z.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "f2dcd1e5b8addb5e"},
+    2: {"executed_flop_per_face": (75792 + 75800 + 75794) / 3, "hbm_bytes_per_face": (377.7 + 468.8 + 467.9) / 3,
+        "sources": ("flux_zc.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "6c8a65adb2a0b429"},
 }
 
 
