@@ -184,21 +184,18 @@ __device__ __forceinline__ void zcface_field(const Geo& g, const double* __restr
 constexpr int kZcLines = 64 * 5 * 5;
 __device__ __forceinline__ int zc_line(int face, int r, int k) { return (face * 5 + r) * 5 + k; }
 
-// Phase 2 for NG field groups (first LDS fields f0a, f0b, f0c) at once: lines of
-// the five t1-neighbours of every face's five t2 rows, in that face's
-// characteristic variables, group g into lb + g * 3 * kZcLines.  Several groups
-// per pass fill the 256 threads better: one group is 320 jobs (two rounds, the
-// second a quarter full), two are 640 (three rounds) and three 960 (four).
-template <typename T, int DIR, int NG, int WP>
-__device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const T* eg, int f0a, int f0b, int f0c,
-                                               T* lb) {
+// Phase 2 for one field group (first LDS field f0): lines of the five
+// t1-neighbours of every face's five t2 rows, in that face's characteristic
+// variables, into lb (320 jobs: two rounds of 256 threads, the second a quarter
+// full).  Building two or three groups per pass fills the rounds better but needs
+// a line buffer per group; with one buffer the FP64 kernel fits two workgroups
+// per CU at two waves per SIMD, which measured 12% faster.
+template <typename T, int DIR, int WP>
+__device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const T* eg, int f0, T* lb) {
   using TG = ZTileGeom<DIR>;
   const int wp = zexp<WP>(g);
   const T eps = T(g.weno_eps);
-  for (int j = threadIdx.x; j < NG * 64 * 5; j += 256) {
-    const int grp = j / (64 * 5), jj = j - grp * (64 * 5);
-    const int f0 = grp == 0 ? f0a : (grp == 1 ? f0b : f0c);
-    T* lg = lb + grp * (3 * kZcLines);
+  for (int jj = threadIdx.x; jj < 64 * 5; jj += 256) {
     const int face = jj / 5, r = jj % 5;
     const int a = face % TG::B, t = face / TG::B;
     const ZEig<T> ez = zeig_load(eg + face * kZEigVals);
@@ -216,9 +213,9 @@ __device__ __forceinline__ void zc_group_lines(const Geo& g, const T* ff, const 
       T ea, eb;
       weno_z_edges(line, eps, wp, ea, eb);
       const int li = zc_line(face, r, k);
-      lg[3 * li] = w[2][k];
-      lg[3 * li + 1] = ea;
-      lg[3 * li + 2] = eb;
+      lb[3 * li] = w[2][k];
+      lb[3 * li + 1] = ea;
+      lb[3 * li + 2] = eb;
     }
   }
 }
@@ -292,12 +289,10 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
                                              const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   using TG = ZTileGeom<DIR>;
   static_assert(TG::B * TG::B * 4 == 256, "four lanes per face");
-  // FP64 builds the three states' lines in one pass and each side's two groups
-  // in one pass (150 KB of LDS, one workgroup per CU at one wave per SIMD); the
-  // FP32 form builds one group per pass and keeps three workgroups per CU
-  constexpr int NGS = sizeof(T) == 8 ? 3 : 1;  // line buffers
+  // one field group's lines per pass (a single line buffer): 76 KB of LDS in
+  // FP64, two workgroups per CU; 39 KB in FP32, three
   __shared__ T ff[TG::NF * TG::NFF];
-  __shared__ T lb[NGS * 3 * kZcLines];
+  __shared__ T lb[3 * kZcLines];
   __shared__ T eg[64 * kZEigVals];
   const int tile = tile_of_block(nper);
   const int Nn = g.n[DIR];
@@ -324,29 +319,20 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
     if (gp == 0) zeig_store(ez, eg + face * kZEigVals);
   }
   __syncthreads();
-  constexpr int L = 3 * kZcLines;
   // the three states first (the collision time needs them); each side's
   // tangential derivatives are reconstructed again just before that side, which
   // keeps fewer values live than holding them from the first pass
   ZFold<T> c;
   {
     T Ql[5], Qr[5], Q0[5], unused[5];
-    if constexpr (NGS == 3) {
-      zc_group_lines<T, DIR, 3, WP>(g, ff, eg, kZQl, kZQr, kZQ0, lb);
-      __syncthreads();
-      zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, Ql, unused, unused);
-      zc_group_gp<T, DIR, false, WP>(g, lb + L, ez, face, sm, sl, Qr, unused, unused);
-      zc_group_gp<T, DIR, false, WP>(g, lb + 2 * L, ez, face, sm, sl, Q0, unused, unused);
-    } else {
-      const int fs[3] = {kZQl, kZQr, kZQ0};
-      T* out[3] = {Ql, Qr, Q0};
+    const int fs[3] = {kZQl, kZQr, kZQ0};
+    T* out[3] = {Ql, Qr, Q0};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        if (i > 0) __syncthreads();  // the previous group's lines have been read
-        zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fs[i], 0, 0, lb);
-        __syncthreads();
-        zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, out[i], unused, unused);
-      }
+    for (int i = 0; i < 3; ++i) {
+      if (i > 0) __syncthreads();  // the previous group's lines have been read
+      zc_group_lines<T, DIR, WP>(g, ff, eg, fs[i], lb);
+      __syncthreads();
+      zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, out[i], unused, unused);
     }
     zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
   }
@@ -357,20 +343,13 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
     const int fd = side == 0 ? kZDn : (side == 1 ? kZDl : kZDr);
     T D[3][5], unused[5];
     __syncthreads();  // the previous pass's lines have been read
-    if constexpr (NGS == 3) {
-      zc_group_lines<T, DIR, 2, WP>(g, ff, eg, fs, fd, 0, lb);
-      __syncthreads();
-      zc_group_gp<T, DIR, true, WP>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
-      zc_group_gp<T, DIR, false, WP>(g, lb + L, ez, face, sm, sl, D[0], unused, unused);
-    } else {
-      zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fs, 0, 0, lb);
-      __syncthreads();
-      zc_group_gp<T, DIR, true, WP>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
-      __syncthreads();
-      zc_group_lines<T, DIR, 1, WP>(g, ff, eg, fd, 0, 0, lb);
-      __syncthreads();
-      zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, D[0], unused, unused);
-    }
+    zc_group_lines<T, DIR, WP>(g, ff, eg, fs, lb);
+    __syncthreads();
+    zc_group_gp<T, DIR, true, WP>(g, lb, ez, face, sm, sl, unused, D[1], D[2]);
+    __syncthreads();
+    zc_group_lines<T, DIR, WP>(g, ff, eg, fd, lb);
+    __syncthreads();
+    zc_group_gp<T, DIR, false, WP>(g, lb, ez, face, sm, sl, D[0], unused, unused);
     zfold_side(c, side, D, K, dt, o);
   }
   T F[5], dF[5];
@@ -397,14 +376,18 @@ __device__ __forceinline__ void flux_zc_body(const Geo& g, const double* __restr
   }
 }
 
-// FP64 holds one wave per SIMD (its registers spill into AGPRs there); the FP32
+// FP64 runs two waves per SIMD (256 VGPRs, with spills): 12% faster at 256^3 than
+// one wave per SIMD holding three line buffers and spilling into AGPRs; the FP32
 // form fits three
+#ifndef HGKS_ZCWAVES_F64
+#define HGKS_ZCWAVES_F64 2
+#endif
 #ifndef HGKS_ZCWAVES_F32
 #define HGKS_ZCWAVES_F32 3
 #endif
 // WP: the WENO-Z exponent fixed at compile time (2), or 0 for the run's parameter
 template <typename T, int DIR, bool STAGE2, bool VAR_MU, int WP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : HGKS_ZCWAVES_F32)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_ZCWAVES_F64 : HGKS_ZCWAVES_F32)))
 flux_zc_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
                const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   if (*stop) return;
