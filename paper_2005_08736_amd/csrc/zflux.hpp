@@ -233,23 +233,26 @@ __host__ __device__ __forceinline__ void zexpect(const T* c, const ZGauss<T>& G,
 }
 
 // <u^p P psi> for p = 0 (r0) and, when BOTH, p = 1 (r1), from the expectations
-// e[n][4] of the u-power coefficients C_n, n < NC.
-template <int NC, bool BOTH, typename T>
+// e[n][4] of the u-power coefficients C_n, n < NC; e[n][1] and e[n][2] are taken
+// as zero for n >= NVW.
+template <int NC, bool BOTH, typename T, int NVW = NC>
 __host__ __device__ __forceinline__ void zrows(const T* M, const T (*e)[4], T* r0, T* r1) {
 #pragma unroll
   for (int p = 0; p < (BOTH ? 2 : 1); ++p) {
     T* r = p ? r1 : r0;
     r[0] = M[p] * e[0][0];
     r[1] = M[p + 1] * e[0][0];
-    r[2] = M[p] * e[0][1];
-    r[3] = M[p] * e[0][2];
+    r[2] = NVW > 0 ? M[p] * e[0][1] : T(0);
+    r[3] = NVW > 0 ? M[p] * e[0][2] : T(0);
     T e4 = M[p + 2] * e[0][0] + M[p] * e[0][3];
 #pragma unroll
     for (int n = 1; n < NC; ++n) {
       r[0] = r[0] + M[n + p] * e[n][0];
       r[1] = r[1] + M[n + p + 1] * e[n][0];
-      r[2] = r[2] + M[n + p] * e[n][1];
-      r[3] = r[3] + M[n + p] * e[n][2];
+      if (n < NVW) {
+        r[2] = r[2] + M[n + p] * e[n][1];
+        r[3] = r[3] + M[n + p] * e[n][2];
+      }
       e4 = e4 + M[n + p + 2] * e[n][0] + M[n + p] * e[n][3];
     }
     r[4] = T(0.5) * e4;
@@ -528,6 +531,21 @@ struct ZOut {
   T F[5], D[5], qF, qD;
 };
 
+// E[C], E[v C], E[w C], E[s C] over the zero-mean Gaussian in (v, w, xi) with
+// variance s2 per component, for C = c0 + cv v + cw w + cvv v^2 + cvw vw + cww w^2
+// + cs s + cvs v s + cws w s and s = v^2 + w^2 + xi^2 of Nd = K + 2 components:
+// E[v^2] = s2, E[s] = Nd s2, E[v^2 s] = (Nd + 2) s2^2, E[s^2] = Nd (Nd + 2) s2^2, and
+// every moment odd in v or w is zero (so cvw never contributes).  The caller
+// passes cq = cvv + cww + Nd cs, Ns2 = Nd s2 and N2s2 = (Nd + 2) s2.
+template <typename T>
+__host__ __device__ __forceinline__ void zexp0(T c0, T cv, T cw, T cq, T cvs, T cws, T s2, T Ns2, T N2s2, T* e) {
+  const T q = s2 * cq;
+  e[0] = c0 + q;
+  e[1] = s2 * (cv + N2s2 * cvs);
+  e[2] = s2 * (cw + N2s2 * cws);
+  e[3] = Ns2 * c0 + N2s2 * q;
+}
+
 // kF, kD of the equilibrium side (eq = true) or of an initial side, from the
 // collision time; the exponentials come from the caller (e1 = exp(-dt/tau),
 // eh = exp(-dt/(2 tau))).
@@ -565,18 +583,37 @@ __host__ __device__ __forceinline__ void zfold(T wF, T wD, const T* r0, const T*
 }
 
 // One side (as zside), folded into o; (U0, V0, W0) is the velocity of Q0.
+// The side is evaluated in its own tangential rest frame, v' = v - V, w' = w - W,
+// with psi' = (1, u, v', w', (u^2 + v'^2 + w'^2 + xi^2)/2); then psi = L psi' with
+//   psi_2 = psi'_2 + V psi'_0,  psi_3 = psi'_3 + W psi'_0,
+//   psi_4 = psi'_4 + V psi'_2 + W psi'_3 + (V^2 + W^2)/2 psi'_0,
+// so moment vectors map back by L, moment data into the frame by L^-1, and a
+// polynomial a.psi has coefficients a' = L^T a there.  Over the zero-mean Gaussian
+// in (v', w', xi) every odd moment vanishes and the rest are closed forms in
+// s2 = 1/(2 lambda) (zexp0): the expectations shrink to a few terms per u-power.
+// The particle velocity of the slope term is (u, v' + V, w' + W), so the
+// tangential slopes add V phi_t1 + W phi_t2 to the u^0 coefficient.
 template <typename T>
 __host__ __device__ __forceinline__ void zside_fold(const ZPrim<T>& s, const T (*D)[5], int half, T K, const T* kF,
                                                     const T* kD, T U0, T V0, T W0, ZOut<T>& o, bool first) {
   const T i2l = T(0.5) / s.lam;
-  ZGauss<T> G;
-  zmom_gauss(G.v, 6, s.V, i2l);
-  zmom_gauss(G.w, 6, s.W, i2l);
-  G.x1 = K * i2l;
-  G.x2 = K * (K + T(2)) * i2l * i2l;
+  const T Nd = K + T(2);  // components of s' = v'^2 + w'^2 + xi^2
+  const T Ns2 = Nd * i2l, N2s2 = (Nd + T(2)) * i2l;
   T M[7];
   zmom_gauss(M, 7, s.U, i2l);
-  const ZSlopeCoef<T> sc = zslope_coef(s.U, s.V, s.W, s.lam, i2l, K);
+  const T V = s.V, W = s.W, kVW = T(0.5) * (V * V + W * W);
+  // slope solve in the rest frame: <a' psi'> = b' with b' = L^-1 b (zslope at V = W = 0)
+  const T Ep = T(0.5) * (s.U * s.U + (K + T(3)) * i2l), c4 = T(8) * s.lam * s.lam / (K + T(3)), tl = T(2) * s.lam;
+  auto solve = [&](const T* b, T* a) {
+    const T b2 = b[2] - V * b[0], b3 = b[3] - W * b[0];
+    const T b4 = b[4] - V * b2 - W * b3 - kVW * b[0];
+    const T B = b[1] - s.U * b[0];
+    a[4] = c4 * (b4 - Ep * b[0] - s.U * B);
+    a[1] = tl * B - s.U * a[4];
+    a[2] = tl * b2;
+    a[3] = tl * b3;
+    a[0] = b[0] - s.U * a[1] - Ep * a[4];
+  };
   T ea[4][4];
   {
     T a[3][5];
@@ -586,37 +623,91 @@ __host__ __device__ __forceinline__ void zside_fold(const ZPrim<T>& s, const T (
       T b[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) b[k] = D[d][k] * ir;
-      zslope(b, s.U, s.V, s.W, sc, a[d]);
+      solve(b, a[d]);
     }
-    zexpect_slopes(a, G, ea);
+    const T* n = a[0];
+    const T* t = a[1];
+    const T* r = a[2];
+    T X[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) X[k] = V * t[k] + W * r[k];
+    zexp0(X[0], t[0] + X[2], r[0] + X[3], t[2] + r[3] + Nd * T(0.5) * X[4], T(0.5) * t[4], T(0.5) * r[4], i2l, Ns2,
+          N2s2, ea[0]);
+    {
+      const T c0 = n[0] + X[1], q = i2l * (Nd * T(0.5) * n[4]);
+      ea[1][0] = c0 + q;
+      ea[1][1] = i2l * (n[2] + t[1]);
+      ea[1][2] = i2l * (n[3] + r[1]);
+      ea[1][3] = Ns2 * c0 + N2s2 * q;
+    }
+    ea[2][0] = n[1] + T(0.5) * X[4];
+    ea[2][1] = i2l * T(0.5) * t[4];
+    ea[2][2] = i2l * T(0.5) * r[4];
+    ea[2][3] = Ns2 * ea[2][0];
+    ea[3][0] = T(0.5) * n[4];
+    ea[3][1] = T(0);
+    ea[3][2] = T(0);
+    ea[3][3] = Ns2 * ea[3][0];
   }
-  // time slope: <(a.u + A) psi> = 0 over the full-space Maxwellian
+  // time slope: <(a.u + A) psi> = 0 over the full-space Maxwellian, solved in the
+  // rest frame from the rows there (b' = -ra' directly)
   T A[5];
   {
-    T ra[5], unused[5], bt[5];
-    zrows<4, false>(M, ea, ra, unused);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) bt[k] = -ra[k];
-    zslope(bt, s.U, s.V, s.W, sc, A);
+    T ra[5], unused[5];
+    zrows<4, false, T, 3>(M, ea, ra, unused);
+    const T B = -ra[1] + s.U * ra[0];
+    A[4] = c4 * (-ra[4] + Ep * ra[0] - s.U * B);
+    A[1] = tl * B - s.U * A[4];
+    A[2] = -tl * ra[2];
+    A[3] = -tl * ra[3];
+    A[0] = -ra[0] - s.U * A[1] - Ep * A[4];
   }
   if (half != 0) zmom_half(M, s.U, s.lam, i2l, T(half));
-  const T wF1 = s.rho * kF[1], wD1 = s.rho * kD[1];
+  // heat flux about U0 in the rest frame: relative tangential velocity of Q0
+  const T dV = V0 - V, dW = W0 - W;
+  auto fold = [&](T wF, T wD, T* r0, T* r1, bool f) {
+    const T h = zheat(r1, r0, U0, dV, dW);
+    r1[4] = r1[4] + V * r1[2] + W * r1[3] + kVW * r1[0];
+    r1[2] = r1[2] + V * r1[0];
+    r1[3] = r1[3] + W * r1[0];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      o.F[k] = f ? wF * r1[k] : o.F[k] + wF * r1[k];
+      o.D[k] = f ? wD * r1[k] : o.D[k] + wD * r1[k];
+    }
+    o.qF = f ? wF * h : o.qF + wF * h;
+    o.qD = f ? wD * h : o.qD + wD * h;
+  };
   {
     T r0[5], r1[5];
-    zrows<4, true>(M, ea, r0, r1);  // a.u
-    zfold(wF1, wD1, r0, r1, U0, V0, W0, o, first);
+    zrows<4, true, T, 3>(M, ea, r0, r1);  // a.u
+    fold(s.rho * kF[1], s.rho * kD[1], r0, r1, first);
   }
   {
     T eA[3][4], r0[5], r1[5];
-    zexpect_phi(A, G, eA);
-    zrows<3, true>(M, eA, r0, r1);  // A
-    zfold(s.rho * kF[2], s.rho * kD[2], r0, r1, U0, V0, W0, o, false);
+    {
+      const T q = i2l * (Nd * T(0.5) * A[4]);
+      eA[0][0] = A[0] + q;
+      eA[0][1] = i2l * A[2];
+      eA[0][2] = i2l * A[3];
+      eA[0][3] = Ns2 * A[0] + N2s2 * q;
+    }
+    eA[1][0] = A[1];
+    eA[1][1] = T(0);
+    eA[1][2] = T(0);
+    eA[1][3] = Ns2 * A[1];
+    eA[2][0] = T(0.5) * A[4];
+    eA[2][1] = T(0);
+    eA[2][2] = T(0);
+    eA[2][3] = Ns2 * eA[2][0];
+    zrows<3, true, T, 1>(M, eA, r0, r1);  // A
+    fold(s.rho * kF[2], s.rho * kD[2], r0, r1, false);
   }
   {
-    T e1[1][4] = {{T(1), s.V, s.W, G.E(0, 0, 1)}};
+    T e1[1][4] = {{T(1), T(0), T(0), Ns2}};
     T r0[5], r1[5];
-    zrows<1, true>(M, e1, r0, r1);  // phi = 1
-    zfold(s.rho * kF[0], s.rho * kD[0], r0, r1, U0, V0, W0, o, false);
+    zrows<1, true, T, 0>(M, e1, r0, r1);  // phi = 1
+    fold(s.rho * kF[0], s.rho * kD[0], r0, r1, false);
   }
 }
 
