@@ -106,22 +106,33 @@ __host__ __device__ __forceinline__ void weno_z_edges(const T* v, T eps, int p, 
   T tau5 = fabs(b0 - b2);
   T r0, r1, r2;
   zratios(tau5, b0, b1, b2, eps, p, r0, r1, r2);
+  // right edge with weights (0.1, 0.6, 0.3) on (r0, r1, r2); the reversed line
+  // (v4, v3, v2, v1, v0) has indicators (b2, b1, b0), so its weights take (r2, r1, r0)
+  const T ab0 = T(0.1) * (T(1) + r0), ab1 = T(0.6) * (T(1) + r1), ab2 = T(0.3) * (T(1) + r2);
+  const T aa0 = T(0.1) * (T(1) + r2), aa1 = T(0.6) * (T(1) + r1), aa2 = T(0.3) * (T(1) + r0);
+  const T sb = ab0 + ab1 + ab2, sa = aa0 + aa1 + aa2;
+  T isb, isa;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    // one reciprocal for both sums (each lies in [1, 1 + max r], so the product
+    // stays far inside the FP64 range)
+    const T ip = recip(sa * sb);
+    isb = sa * ip;
+    isa = sb * ip;
+  } else {
+    isb = recip(sb);
+    isa = recip(sa);
+  }
   {
-    T a0 = T(0.1) * (T(1) + r0), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r2);
-    const T isum = recip(a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[0] - T(7.0 / 6.0) * v[1] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[1] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[3];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[3] - T(1.0 / 6.0) * v[4];
-    eb = (a0 * q0 + a1 * q1 + a2 * q2) * isum;
+    eb = (ab0 * q0 + ab1 * q1 + ab2 * q2) * isb;
   }
   {
-    // reversed line (v4, v3, v2, v1, v0): indicators (b2, b1, b0)
-    T a0 = T(0.1) * (T(1) + r2), a1 = T(0.6) * (T(1) + r1), a2 = T(0.3) * (T(1) + r0);
-    const T isum = recip(a0 + a1 + a2);
     T q0 = T(1.0 / 3.0) * v[4] - T(7.0 / 6.0) * v[3] + T(11.0 / 6.0) * v[2];
     T q1 = T(-1.0 / 6.0) * v[3] + T(5.0 / 6.0) * v[2] + T(1.0 / 3.0) * v[1];
     T q2 = T(1.0 / 3.0) * v[2] + T(5.0 / 6.0) * v[1] - T(1.0 / 6.0) * v[0];
-    ea = (a0 * q0 + a1 * q1 + a2 * q2) * isum;
+    ea = (aa0 * q0 + aa1 * q1 + aa2 * q2) * isa;
   }
 }
 
