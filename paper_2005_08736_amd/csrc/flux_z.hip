@@ -24,7 +24,7 @@
 
 namespace hgks {
 
-template <typename T, int DIR, bool STAGE2, bool VAR_MU>
+template <typename T, int DIR, bool STAGE2, bool VAR_MU, bool RECOMP>
 __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restrict__ q, T* __restrict__ fl,
                                             const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   using TG = ZTileGeom<DIR>;
@@ -49,9 +49,13 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   const T dt = T(*dtp);
   const T K = T(g.K);
   T dum, tok = T(0);
-  // values (and t2-derivatives) of Q_l, Q_r and Q0 first: the collision time needs them
-  // (the two Gauss points with the same t1 point split each pair of WENO-Z edge
-  // evaluations between them, zgp_pair)
+  // Values of Q_l, Q_r and Q0 first: the collision time needs them (the two
+  // Gauss points with the same t1 point split each pair of WENO-Z edge
+  // evaluations between them, zgp_pair).  The sides' values and t2-derivatives
+  // are either held from here through the side loop with the three sides'
+  // primitive states (RECOMP = false), or evaluated again in each side's trip by
+  // the same calls, which give the same bits (RECOMP = true): three more WENO-Z
+  // edge evaluations per lane and side for 200 B less scratch per lane.
   T Ql[5], Qr[5], Q0[5], Ql2[5], Qr2[5], Q02[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k)
@@ -61,6 +65,7 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
   zgp_field<T, DIR, false>(g, ff, ed, kZQ0 + 4, a, t, sm, sl, Q0[4], dum, Q02[4], tok);
   ZFold<T> c;
   zfold_begin<VAR_MU>(g, Q0, Ql, Qr, dt, c);
+  const T U0 = c.s0.U, V0 = c.s0.V, W0 = c.s0.W;
   ZOut<T> o;
   // one side per trip of a loop that is not unrolled: the scheduler cannot
   // overlap one side's reconstruction with another side's moments, and a single
@@ -73,12 +78,38 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
     const int fd = side == 0 ? kZDn : (side == 1 ? kZDl : kZDr);
     const int fs = side == 0 ? kZQ0 : (side == 1 ? kZQl : kZQr);
     T D[3][5];
+    ZPrim<T> sp;
+    if (!RECOMP) {
+      sp = side == 0 ? c.s0 : (side == 1 ? c.sl : c.sr);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      zgp_pair<T, DIR, true>(g, ff, ed, fd + k, fs + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
-      D[2][k] = side == 0 ? Q02[k] : (side == 1 ? Ql2[k] : Qr2[k]);
+      for (int k = 0; k < 5; ++k) D[2][k] = side == 0 ? Q02[k] : (side == 1 ? Ql2[k] : Qr2[k]);
+    } else {
+      T Qs[5];
+      if (side == 0) {
+        zgp_pair<T, DIR, false>(g, ff, ed, fs + 0, fs + 1, aa, t, sm, sl, Qs[0], D[2][0], Qs[1], D[2][1], tok);
+        zgp_pair<T, DIR, false>(g, ff, ed, fs + 2, fs + 3, aa, t, sm, sl, Qs[2], D[2][2], Qs[3], D[2][3], tok);
+        zgp_field<T, DIR, false>(g, ff, ed, fs + 4, aa, t, sm, sl, Qs[4], dum, D[2][4], tok);
+      } else {
+        // the fifth field pairs with itself: the same row formula as the first pass
+#pragma unroll
+        for (int k = 0; k < 5; k += 2) {
+          const int k2 = k + 1 < 5 ? k + 1 : k;
+          T v2, d2;
+          zgp_pair<T, DIR, false>(g, ff, ed, fs + k, fs + k2, aa, t, sm, sl, Qs[k], D[2][k], v2, d2, tok);
+          if (k + 1 < 5) {
+            Qs[k + 1] = v2;
+            D[2][k + 1] = d2;
+          }
+        }
+      }
+      sp = zprim(g, Qs);
     }
-    zfold_side(c, side, D, K, dt, o);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      zgp_pair<T, DIR, true>(g, ff, ed, fd + k, fs + k, aa, t, sm, sl, D[0][k], dum, D[1][k], dum, tok);
+    T kF[3], kD[3];
+    zfd_coef(dt, c.tau, c.e1, c.eh, side == 0, kF, kD);
+    zside_fold(sp, D, side == 0 ? 0 : (side == 1 ? +1 : -1), K, kF, kD, U0, V0, W0, o, side == 0);
   }
   T F[5], dF[5];
   zfold_end(g, o, F, dF);
@@ -108,6 +139,7 @@ __device__ __forceinline__ void flux_z_body(const Geo& g, const double* __restri
 #ifndef HGKS_ZWAVES
 #define HGKS_ZWAVES 2
 #endif
+
 #ifndef HGKS_ZWAVES_F32
 #define HGKS_ZWAVES_F32 4
 #endif
@@ -117,7 +149,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? HGKS_ZWAVES : HGKS_ZWAVES_F3
 flux_z_kernel(Geo g, const double* __restrict__ q, T* __restrict__ fl, const int* __restrict__ stop,
               const double* __restrict__ dtp, int nt1, int nt2, int nper) {
   if (*stop) return;
-  flux_z_body<T, DIR, STAGE2, VAR_MU>(g, q, fl, dtp, nt1, nt2, nper);
+  // side values evaluated again in each side's trip: FP64 stage 1 only (measured
+  // faster there; slower in the FP64 stage-2 launch and in the FP32 form, whose
+  // spills are smaller or cheaper)
+  constexpr bool RECOMP = sizeof(T) == 8 && !STAGE2;
+  flux_z_body<T, DIR, STAGE2, VAR_MU, RECOMP>(g, q, fl, dtp, nt1, nt2, nper);
 }
 
 template <typename T, int DIR, bool STAGE2, bool VAR_MU>
