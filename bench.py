@@ -58,16 +58,16 @@ FLUX_Z_FLOPS_PER_FACE = 1e5 / 6
 # factors make the same counters read the known 671 MB in / 671 MB out of the
 # library's copy kernel.  Valid only for the kernel sources with this digest
 # (profiles/flux_fused_tgv256_kernels.md).
-FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.8
+FLUX_STAGE1_HBM_BYTES_PER_FACE = 150.9
 FLUX_COUNTERS_SOURCE_DIGEST = "5cb3bf1de8040b20"
 # The same counters for the stage-1 FP64 flux of mode Z and of its characteristic
 # form at 256^3 (mean of the three directions; profiles/flux_z_isotropic256_kernels.md
 # and profiles/flux_zc_shocklet256_kernels.md), per mode: executed FP64 operations
 # per face (FMA = 2), HBM bytes per face, and the digest of the sources they hold for.
 FLUX_Z_COUNTERS = {
-    1: {"executed_flop_per_face": (36895 + 36897 + 36896) / 3, "hbm_bytes_per_face": (2310.3 + 2517.6 + 2538.0) / 3,
-        "sources": ("flux_z.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "4d578e2665b724f5"},
-    2: {"executed_flop_per_face": (71473 + 71481 + 71475) / 3, "hbm_bytes_per_face": (4049.2 + 4290.4 + 4330.7) / 3,
+    1: {"executed_flop_per_face": (43299 + 43301 + 43300) / 3, "hbm_bytes_per_face": (549.7 + 647.8 + 600.8) / 3,
+        "sources": ("flux_z.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "de5653f500932ddc"},
+    2: {"executed_flop_per_face": (71473 + 71481 + 71475) / 3, "hbm_bytes_per_face": (4040.9 + 4291.0 + 4332.6) / 3,
         "sources": ("flux_zc.hip", "ztile.hpp", "zflux.hpp", "device_common.hpp"), "digest": "fbd92d9b7bf2b700"},
 }
 
